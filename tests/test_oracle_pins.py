@@ -1,0 +1,365 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test names what it pins.  Nothing here needs a GPU.
+"""
+
+import itertools
+from math import comb, pi, sqrt
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.optimize
+import scipy.sparse as sps
+
+from oracle import chain, chebyshev, dense, lanczos
+from paper_2005_09534_amd import workloads
+
+
+# ---------------------------------------------------------------------------
+# basis and rank: brute force, combinatorics
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_basis_matches_combinations(L):
+    """Sz=0 basis = all L/2-subsets of the L sites, as ascending integers."""
+    b = chain.basis(L)
+    ref = sorted(sum(1 << i for i in c) for c in itertools.combinations(range(L), L // 2))
+    assert len(b) == comb(L, L // 2) == chain.sector_dim(L)
+    assert b.tolist() == ref
+    assert b[0] == (1 << (L // 2)) - 1
+    assert b[-1] == ((1 << (L // 2)) - 1) << (L // 2)
+
+
+@pytest.mark.parametrize("L", [4, 10, 16, 20])
+def test_rank_is_colex_combinadic(L):
+    """rank(s) = sum_t C(p_t, t) over set bits p_1 < p_2 < ... (t from 1):
+    the colexicographic rank, which is the ascending-integer order."""
+    b = chain.basis(L)
+    rng = np.random.default_rng(L)
+    pick = rng.choice(len(b), size=min(len(b), 500), replace=False)
+    r = chain.rank(b[pick], b)
+    for row, st in zip(pick, b[pick]):
+        bits = [i for i in range(L) if (int(st) >> i) & 1]
+        assert sum(comb(p, t + 1) for t, p in enumerate(bits)) == row
+    assert (r == pick).all()
+    # states outside the sector are reported absent
+    bad = np.array([0, (1 << L) - 1, 1], dtype=b.dtype)
+    assert (chain.rank(bad, b) == -1).all()
+
+
+# ---------------------------------------------------------------------------
+# H: Kronecker-product construction in the full 2^L space
+# ---------------------------------------------------------------------------
+
+def _kron_site(op, i, L):
+    """Operator op on the site carried by bit i of the basis integer."""
+    return sps.kron(sps.kron(sps.identity(1 << (L - 1 - i)), sps.csr_matrix(op)),
+                    sps.identity(1 << i)).tocsr()
+
+
+def _full_H(L, J1, J2, Delta, h):
+    # single-site basis ordered (bit 0 = down, bit 1 = up)
+    sx = 0.5 * np.array([[0, 1], [1, 0]], dtype=complex)
+    sy = 0.5 * np.array([[0, -1j], [1j, 0]], dtype=complex)
+    sz = 0.5 * np.array([[-1, 0], [0, 1]], dtype=complex)
+    n = 1 << L
+    H = sps.csr_matrix((n, n), dtype=complex)
+    S = {a: [_kron_site(op, i, L) for i in range(L)] for a, op in (("x", sx), ("y", sy), ("z", sz))}
+    for l, J in ((1, J1), (2, J2)):
+        for i in range(L):
+            j = (i + l) % L
+            H = H + J * (S["x"][i] @ S["x"][j] + S["y"][i] @ S["y"][j] + Delta * S["z"][i] @ S["z"][j])
+    for i in range(L):
+        H = H + h[i] * S["z"][i]
+    Sz = sum(S["z"])
+    comm = abs(H @ Sz - Sz @ H).max()
+    H = H.toarray()
+    assert np.abs(H.imag).max() < 1e-15
+    return H.real, comm
+
+
+@pytest.mark.parametrize("L,J2", [(4, 0.0), (6, 0.0), (6, 1.0), (8, 0.7), (10, 1.0)])
+def test_csr_matches_kronecker(L, J2):
+    """Sz=0 block of the full-space H equals the oracle's CSR; Sz is
+    conserved; H is exactly symmetric."""
+    rng = np.random.default_rng(100 + L)
+    Delta = float(rng.uniform(0.2, 1.5))
+    h = rng.uniform(-3, 3, L)
+    Hf, comm = _full_H(L, 1.0, J2, Delta, h)
+    assert comm < 1e-13
+    b = chain.basis(L).astype(np.int64)
+    Hs = chain.hamiltonian_csr(L, 1.0, J2, Delta, h)
+    assert np.abs(Hs.toarray() - Hf[np.ix_(b, b)]).max() < 1e-13
+    assert (Hs != Hs.T).nnz == 0
+
+
+@pytest.mark.parametrize("L,J2,Delta,expect", [(8, 0.0, 0.7, -14.0), (8, 1.0, 0.7, -28.0),
+                                               (10, 1.0, 0.7, -98.0), (12, 0.0, 1.0, None),
+                                               (14, 1.0, 0.55, None)])
+def test_trace_closed_form(L, J2, Delta, expect):
+    """Tr H = -N (J1+J2) Delta L / (4(L-1)): in Sz=0 every pair of distinct
+    sites has <Sz_i Sz_j> = -1/(4(L-1)), and sum_r Sz_i = 0, so h drops out."""
+    h = np.random.default_rng(L).uniform(-5, 5, L)
+    N = comb(L, L // 2)
+    tr = float(chain.diagonal(L, 1.0, J2, Delta, h).sum())
+    closed = -N * (1.0 + J2) * Delta * L / (4.0 * (L - 1))
+    assert abs(tr - closed) < 1e-9 * max(1.0, abs(closed))
+    if expect is not None:
+        assert abs(closed - expect) < 1e-12
+
+
+def _free_fermion_spectrum(L, J1=1.0):
+    """XX chain (Delta = 0, J2 = 0, h = 0) in the Sz=0 sector by
+    Jordan-Wigner: L/2 fermions, single-particle energies J1 cos k with
+    k = 2 pi (n + phi)/L, phi = 0 if L/2 is odd (periodic), 1/2 if L/2 is
+    even (antiperiodic, the boundary bond picks up (-1)^(N_f - 1))."""
+    Nf = L // 2
+    phi = 0.0 if Nf % 2 == 1 else 0.5
+    eps = J1 * np.cos(2 * pi * (np.arange(L) + phi) / L)
+    return np.sort([eps[list(c)].sum() for c in itertools.combinations(range(L), Nf)])
+
+
+@pytest.mark.parametrize("L", [4, 6, 8, 10, 12])
+def test_xx_chain_free_fermions(L):
+    H = chain.hamiltonian_csr(L, 1.0, 0.0, 0.0, np.zeros(L))
+    w = dense.full_spectrum(H)
+    ff = _free_fermion_spectrum(L)
+    assert np.abs(w - ff).max() < 1e-12
+    if L == 4:
+        assert np.allclose(w, [-sqrt(2), 0, 0, 0, 0, sqrt(2)], atol=1e-14)
+
+
+def test_diagonal_special_case():
+    """J1 = J2 = 0: H is diagonal with E_r = sum_i h_i (n_i - 1/2)."""
+    L = 10
+    h = np.random.default_rng(5).uniform(-2, 2, L)
+    b = chain.basis(L).astype(np.int64)
+    E = np.array([sum(h[i] * (((s >> i) & 1) - 0.5) for i in range(L)) for s in b])
+    H = chain.hamiltonian_csr(L, 0.0, 0.0, 1.0, h)
+    assert H.nnz == len(b)
+    assert np.abs(H.diagonal() - E).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# the filter: Dirichlet-kernel closed form, eigenvector action
+# ---------------------------------------------------------------------------
+
+def _dirichlet(u, K):
+    u = np.asarray(u, dtype=np.float64)
+    out = np.empty_like(u)
+    small = np.abs(np.sin(u / 2)) < 1e-12
+    out[small] = 2 * K + 1
+    out[~small] = np.sin((K + 0.5) * u[~small]) / np.sin(u[~small] / 2)
+    return out
+
+
+def _P_closed(x, sigma, K):
+    """P_K(cos th) = [D_K(th - a) + D_K(th + a)] / [D_K(0) + D_K(2a)],
+    sigma = cos a, D_K(u) = sin((K+1/2)u)/sin(u/2): since
+    1 + 2 sum_{n<=K} cos(n a) cos(n th) = (D_K(th-a) + D_K(th+a))/2."""
+    a = np.arccos(sigma)
+    th = np.arccos(np.asarray(x, dtype=np.float64))
+    return (_dirichlet(th - a, K) + _dirichlet(th + a, K)) / (_dirichlet(np.array([0.0]), K) + _dirichlet(np.array([2 * a]), K))
+
+
+@pytest.mark.parametrize("K", [1, 2, 22, 23, 200])
+@pytest.mark.parametrize("sigma", [0.0, 0.3, -0.71])
+def test_filter_closed_form(K, sigma):
+    x = np.linspace(-0.999, 0.999, 301)
+    assert np.abs(chebyshev.P_of_x(x, sigma, K) - _P_closed(x, sigma, K)).max() < 1e-12
+    assert abs(chebyshev.P_of_x([sigma], sigma, K)[0] - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("K", [21, 22, 200, 201])
+def test_norm_D_at_centre(K):
+    """At sigma = 0: D = K + 1 for even K, K for odd K."""
+    assert abs(chebyshev.norm_D(0.0, K) - (K + 1 if K % 2 == 0 else K)) < 1e-9
+
+
+def test_side_lobes_below_p():
+    """The threshold p = 0.17 sits above every side lobe of P (largest
+    positive lobe ~0.128 at large K); side lobes dip to about -0.217."""
+    K = 400
+    x = np.cos(np.linspace(0, pi, 200001))
+    P = _P_closed(x, 0.0, K)
+    main = np.abs(np.arccos(x) - pi / 2) < 2 * pi / (2 * K + 1)
+    assert P[~main].max() < 0.17
+    assert 0.12 < P[~main].max() < 0.135
+    assert -0.225 < P.min() < -0.21
+
+
+@pytest.mark.parametrize("K,sigma", [(0, 0.0), (1, 0.2), (7, 0.0), (60, 0.35), (151, -0.1)])
+def test_filter_acts_on_eigenvectors(K, sigma):
+    """P(H~) v = P(lambda~) v for every eigenvector v of H; pins the forward
+    recurrence (incl. the rescale) against the scalar closed form."""
+    L = 8
+    h = np.random.default_rng(3).uniform(-2, 2, L)
+    H = chain.hamiltonian_csr(L, 1.0, 0.5, 0.8, h)
+    w, V = np.linalg.eigh(H.toarray())
+    E0, E1 = lanczos.widened_bounds(w[0], w[-1], 1e-3)
+    a, b = chebyshev.rescale_coeffs(E0, E1)
+    Y = chebyshev.filter_block(H, V, E0, E1, sigma, K)
+    Pw = _P_closed(a * w + b, sigma, K) if K > 0 else np.ones_like(w)
+    assert np.abs(Y - V * Pw).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# density of states and the order rule
+# ---------------------------------------------------------------------------
+
+def test_gamma_is_infinite_temperature_width():
+    """Gamma^2 = Tr(H^2)/2^L - (Tr H/2^L)^2 exactly in the full space for
+    L >= 5 (all bonds distinct): each bond adds J^2 (2 + Delta^2)/16, each
+    field h_i^2/4.  And at J1 = 1 with sum h^2 = L W^2/3 it equals the
+    paper's Gamma = sqrt(L[(1+J2^2)/8 + Delta^2 (1+J2^2)/16 + W^2/12])."""
+    L, J2, Delta = 8, 0.6, 0.8
+    h = np.random.default_rng(9).uniform(-3, 3, L)
+    Hf, _ = _full_H(L, 1.0, J2, Delta, h)
+    n = Hf.shape[0]
+    var = np.trace(Hf @ Hf) / n - (np.trace(Hf) / n) ** 2
+    assert abs(chebyshev.dos_gamma(L, 1.0, J2, Delta, h) ** 2 - var) < 1e-12
+    W = 2.5
+    hW = np.full(L, W / sqrt(3.0))
+    paper = sqrt(L * ((1 + J2 ** 2) / 8 + Delta ** 2 * (1 + J2 ** 2) / 16 + W ** 2 / 12))
+    assert abs(chebyshev.dos_gamma(L, 1.0, J2, Delta, hW) - paper) < 1e-12
+
+
+def test_n_states_between_is_integral_of_rho():
+    N, Ebar, G, E0, E1 = 12870, -0.3, 3.1, -14.0, 13.0
+    x_lo, x_hi = -0.05, 0.08
+    num, _ = scipy.integrate.quad(lambda x: chebyshev.rho_tilde(x, N, Ebar, G, E0, E1), x_lo, x_hi,
+                                  epsabs=1e-12, epsrel=1e-12)
+    Elo = 0.5 * (x_lo * (E1 - E0) + E1 + E0)
+    Ehi = 0.5 * (x_hi * (E1 - E0) + E1 + E0)
+    assert abs(chebyshev.n_states_between(N, Ebar, G, Elo, Ehi) - num) < 1e-8 * num
+    # total mass: all N states
+    assert abs(chebyshev.n_states_between(N, Ebar, G, -1e3, 1e3) - N) < 1e-6
+
+
+@pytest.mark.parametrize("K,sigma", [(50, 0.0), (333, 0.25), (2000, -0.4)])
+def test_lobe_edges_hit_p(K, sigma):
+    lo, hi = chebyshev.lobe_edges(sigma, K, 0.17)
+    assert lo < sigma < hi
+    assert abs(_P_closed([lo], sigma, K)[0] - 0.17) < 1e-9
+    assert abs(_P_closed([hi], sigma, K)[0] - 0.17) < 1e-9
+    # half-width against the asymptotic u*/(K+1/2) sin(alpha), sin(u*)/u* = 0.17
+    ustar = scipy.optimize.brentq(lambda u: np.sin(u) / u - 0.17, 2.0, 3.0)
+    assert abs(ustar - 2.6704) < 1e-3
+    approx = ustar / (K + 0.5) * sqrt(1 - sigma ** 2)
+    assert abs(0.5 * (hi - lo) - approx) < 0.02 * approx
+
+
+def test_choose_K_asymptotics_and_scaling():
+    """K ~ 2 u* rho~(sigma) sqrt(1-sigma^2) / N_ev - 1/2 at large K, and
+    N_ev -> a N_ev gives K -> K/a (Supplement, "Benchmark")."""
+    N, Ebar, G, E0, E1 = 705432, -2.6, 7.5, -29.0, 27.0
+    sigma = 0.0
+    rho = chebyshev.rho_tilde(sigma, N, Ebar, G, E0, E1)
+    ustar = 2.67040
+    for nev in (100, 400):
+        K = chebyshev.choose_K(nev, sigma, 0.17, N, Ebar, G, E0, E1)
+        approx = 2 * ustar * rho / nev - 0.5
+        assert abs(K - approx) < 0.01 * approx
+        f = lambda k: chebyshev.n_P(k, sigma, 0.17, N, Ebar, G, E0, E1)
+        assert f(K) >= nev > f(K + 1)
+    K1 = chebyshev.choose_K(100, sigma, 0.17, N, Ebar, G, E0, E1)
+    K2 = chebyshev.choose_K(200, sigma, 0.17, N, Ebar, G, E0, E1)
+    assert abs(K2 / K1 - 0.5) < 0.01
+
+
+# ---------------------------------------------------------------------------
+# the solve: dense diagonalisation, invariants, special cases
+# ---------------------------------------------------------------------------
+
+def _dense_check(L, J1, J2, Delta, h, nev, s, K=None, seed=0):
+    res = lanczos.solve(L, J1, J2, Delta, h, nev, s, K=K, rng_seed=seed)
+    H = chain.hamiltonian_csr(L, J1, J2, Delta, h)
+    Ed, Vd = dense.nearest_dense(H, res["sigma_H"], nev)
+    normH = max(abs(res["E0"]), abs(res["E1"]))
+    return res, H, Ed, Vd, normH
+
+
+def test_solve_c1_vs_dense():
+    """The C1 workload (L=12 XXZ, W=3, N_ev=20, s=4, K=200): eigenvalues
+    equal the 20 nearest the middle of the spectrum (main text claim)."""
+    wl = workloads.c1()
+    c = wl.chains[0]
+    res, H, Ed, Vd, normH = _dense_check(c.L, c.J1, c.J2, c.Delta, c.h, wl.nev, wl.block, K=wl.K)
+    assert res["nconv"] >= wl.nev
+    assert np.abs(res["E"] - Ed).max() <= 1e-10 * normH
+    assert res["resid"].max() <= 1e-8 * normH
+    # eigenvectors: |<u, v>| = 1 up to the Davis-Kahan bound
+    ov = np.abs(np.sum(res["V"] * Vd, axis=0))
+    gaps = np.array([np.min(np.abs(np.delete(dense.full_spectrum(H), np.argmin(np.abs(dense.full_spectrum(H) - e))) - e)) for e in Ed])
+    assert (1 - ov <= (res["resid"] / gaps) ** 2 + 1e-10).all()
+
+
+@pytest.mark.parametrize("L,J2,Delta,W,nev,s", [(10, 0.0, 1.0, 2.0, 10, 2), (12, 1.0, 0.55, 4.0, 16, 4),
+                                                 (12, 0.0, 1.0, 1.0, 12, 1), (10, 1.0, 1.0, 6.0, 8, 8)])
+def test_solve_auto_K_vs_dense(L, J2, Delta, W, nev, s):
+    h = workloads.fields(L, W, 40 + L)
+    res, H, Ed, Vd, normH = _dense_check(L, 1.0, J2, Delta, h, nev, s)
+    assert np.abs(res["E"] - Ed).max() <= 1e-10 * normH
+    assert res["resid"].max() <= 1e-8 * normH
+
+
+def test_lanczos_invariants():
+    """Q^T Q = I, T symmetric, theta <= 1, converged theta = P(lambda~)."""
+    L, nev, s = 12, 12, 4
+    h = workloads.fields(L, 3.0, 11)
+    res = lanczos.solve(L, 1.0, 0.0, 1.0, h, nev, s)
+    Q, T = res["Qm"], res["T"]
+    assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 1e-13
+    assert np.abs(T - T.T).max() == 0.0
+    assert res["theta"].max() <= 1.0 + 1e-12
+    H = chain.hamiltonian_csr(L, 1.0, 0.0, 1.0, h)
+    a, b = chebyshev.rescale_coeffs(res["E0w"], res["E1w"])
+    th = _P_closed(a * res["E"] + b, res["sigma_t"], res["K"])
+    top = np.sort(res["theta"])[::-1][:nev]
+    assert np.abs(np.sort(th)[::-1] - top).max() < 1e-8
+
+
+def test_solve_diagonal_case_is_a_sort():
+    """J1 = J2 = 0: the answer is the N_ev basis states with E nearest the
+    target, and the eigenvectors are unit vectors."""
+    L, nev = 10, 8
+    h = workloads.fields(L, 2.0, 77)
+    b = chain.basis(L).astype(np.int64)
+    E = np.array([sum(h[i] * (((st >> i) & 1) - 0.5) for i in range(L)) for st in b])
+    sigma = 0.5 * (E.min() + E.max())
+    res = lanczos.solve(L, 0.0, 0.0, 1.0, h, nev, 2, sigma_H=sigma)
+    idx = np.lexsort((E, np.abs(E - sigma)))[:nev]
+    assert np.abs(np.sort(E[idx]) - res["E"]).max() < 1e-10
+    V = np.abs(res["V"])
+    assert np.abs(V.max(axis=0) - 1.0).max() < 1e-8
+
+
+def test_convergence_within_paper_cap_s1():
+    """s = 1 with the paper's own rule (window of N_ev, 2.8 N_ev cap):
+    converges with m < 2.8 N_ev (Supplement, "Convergence of POLFED")."""
+    L, nev = 12, 20
+    h = workloads.fields(L, 3.0, 7)
+    res = lanczos.solve(L, 1.0, 0.0, 1.0, h, nev, 1, nev_window=nev, max_cols=int(2.8 * nev))
+    assert res["nconv"] >= nev
+    assert res["m"] < 2.8 * nev
+
+
+def test_shift_invert_matches_dense():
+    L = 12
+    h = workloads.fields(L, 2.0, 3)
+    H = chain.hamiltonian_csr(L, 1.0, 1.0, 1.0, h)
+    w = dense.full_spectrum(H)
+    sig = 0.5 * (w[0] + w[-1])
+    a, _ = dense.nearest_dense(H, sig, 30, vectors=False)
+    b, V = dense.nearest_shift_invert(H, sig, 30)
+    assert np.abs(a - b).max() < 1e-10
+    assert np.abs(H @ V - V * b).max() < 1e-9
+
+
+def test_seed_and_block_invariance():
+    L, nev = 12, 10
+    h = workloads.fields(L, 2.5, 21)
+    r1 = lanczos.solve(L, 1.0, 0.0, 1.0, h, nev, 2, rng_seed=1)
+    r2 = lanczos.solve(L, 1.0, 0.0, 1.0, h, nev, 4, rng_seed=2)
+    assert np.abs(r1["E"] - r2["E"]).max() < 1e-10 * max(abs(r1["E0"]), abs(r1["E1"]))
