@@ -1,0 +1,244 @@
+/*
+ * polfed.h -- C ABI of libpolfed: the POLFED hot path on AMD MI355X (gfx950).
+ *
+ * POLFED (polynomially filtered exact diagonalisation; Sierant, Lewenstein,
+ * Zakrzewski, arXiv:2005.09534) finds the N_ev eigenpairs nearest an energy
+ * target of the disordered spin-1/2 chain of eq. (XXZ) in its Sz=0 sector:
+ * block Lanczos, eqs. (Lan1)-(Lan2), applied to the Chebyshev filter
+ * P^K_sigma(H~) of eq. (polyTransf), with full reorthogonalisation and a final
+ * Rayleigh-Ritz step (main text, "POLFED algorithm"; Supplement,
+ * "Convergence of POLFED" and "Technical details").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every call returns int.  0 = POLFED_OK; >0 = warning, outputs
+ *   written but flagged; <0 = error, outputs untouched.  The message of the
+ *   last error on a context is returned by polfed_last_error().
+ * - Basis: a Sz=0 basis state is an L-bit integer, bit i <-> site i+1, bit
+ *   set <-> S^z = +1/2.  Rows of H are ordered by ascending state integer, so
+ *   row r holds the r-th smallest L-bit integer with L/2 set bits.
+ * - H: the literal double sum of eq. (XXZ) over l = 1,2 and i = 1..L with
+ *   periodic sites; off-diagonal elements +J_l/2 between states that differ
+ *   by swapping an antiparallel pair (Supplement, "Technical details").
+ * - Rescaled operator: H~ = a H + b with a = 2/(E1-E0), b = -(E0+E1)/(E1-E0)
+ *   (main text, "POLFED algorithm").  sigma_tilde is a target in H~ units.
+ * - Vector blocks passed to stage calls are DEVICE pointers, row-major
+ *   (n rows x nvec columns, row r's nvec values contiguous), FP64 (double)
+ *   or FP32 (float) as the precision argument says.  Stage calls are
+ *   asynchronous on the context's stream (polfed_set_stream) unless stated.
+ * - Ownership: callers allocate every input and output.  The library
+ *   allocates and frees only device workspace held by the context.  A
+ *   context is used by one host thread at a time.
+ * - Sizes: L even, 4 <= L <= 30 (J2 != 0 needs L >= 6).  Block widths
+ *   (nvec, block_size) are powers of two from 1 to 64.
+ */
+#ifndef POLFED_H
+#define POLFED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum polfed_status {
+  POLFED_OK = 0,
+  POLFED_NOT_CONVERGED = 1, /* best pairs returned; info->n_conv met tol */
+  POLFED_EINVAL = -1,       /* invalid argument (message says which)     */
+  POLFED_ENOMEM = -2,       /* device allocation failed                  */
+  POLFED_EDEVICE = -3,      /* HIP runtime error                         */
+  POLFED_EBOUNDS = -4,      /* spectral bounds too tight: filter blew up */
+  POLFED_EBREAKDOWN = -5    /* Lanczos block could not be refilled       */
+};
+
+typedef struct polfed_ctx polfed_ctx;
+
+/* The chain of eq. (XXZ).  h: caller-owned host array of length L, read
+ * during the call only. */
+typedef struct {
+  int L;
+  double J1, J2, Delta;
+  const double *h;
+} polfed_model;
+
+/* Solver options.  polfed_default_opts() fills the defaults named here. */
+typedef struct {
+  int target_kind;        /* 0: target = rescaled energy eps in (0,1),
+                             sigma_H = E0 + eps (E1 - E0) with the Lanczos
+                             extremes; 1: target = absolute energy sigma_H  */
+  double target;          /* default 0.5 (middle of the spectrum)          */
+  int block_size;         /* s in {1,2,4,...,64}; 0 = autotuned             */
+  long long K;            /* filter order; 0 = from the density of states  */
+  double p;               /* threshold on theta; 0 -> 0.17                  */
+  int precision;          /* 0: FP64 filter; 1: FP32 filter, FP64 Lanczos,
+                             Rayleigh-Ritz and residuals + FP64 refinement  */
+  double window_factor;   /* filter window sized for ceil(f N_ev)
+                             eigenvalues; 0 -> 1.5                          */
+  int max_cols;           /* Lanczos columns; 0 -> 4 N_win + 6 s           */
+  double tol;             /* residual target relative to ||H||; 0 -> 1e-10 */
+  double eta;             /* bounds margin, fraction of E1-E0; 0 -> 1e-3   */
+  int bounds_steps;       /* bounds Lanczos steps; 0 -> 200                 */
+  unsigned long long seed;/* start-block generator key                     */
+} polfed_opts;
+
+/* Per-solve record (all times in seconds, wall clock on the host). */
+typedef struct {
+  double E0, E1;          /* Lanczos extremes of H                          */
+  double E0w, E1w;        /* widened bounds used for H~                     */
+  double sigma_energy;    /* target in H units                              */
+  double sigma_tilde;     /* target in H~ units                             */
+  double normH;           /* max(|E0|, |E1|)                                */
+  long long K;            /* filter order used                              */
+  int nev_window;         /* eigenvalues the window was sized for           */
+  int block_size;         /* s used                                         */
+  int m;                  /* Lanczos blocks at stop                         */
+  int n_conv;             /* pairs with residual <= tol ||H||              */
+  int refine_passes;      /* FP64 refinement passes (precision 1)           */
+  double max_resid;       /* max returned residual (H units)                */
+  double t_bounds, t_filter, t_orth, t_eig, t_rr, t_refine, t_total;
+  double hv_apps;         /* H~ applications to single vectors              */
+  double filter_bytes;    /* algorithmic bytes moved by the filter kernels  */
+  double filter_gpu_s;    /* filter kernel time by HIP events on the stream */
+  double filter_launches; /* Chebyshev step kernels launched                */
+} polfed_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` (hipSetDevice is called).  The
+ * context owns a non-blocking stream and its device workspace. */
+int polfed_create(int device, polfed_ctx **out);
+int polfed_destroy(polfed_ctx *ctx);
+/* Message of the last error on ctx ("" if none); owned by ctx. */
+const char *polfed_last_error(const polfed_ctx *ctx);
+/* Run subsequent calls on `stream` (a hipStream_t; NULL is HIP's null
+ * stream).  Until this is called, calls run on the context's own
+ * non-blocking stream. */
+int polfed_set_stream(polfed_ctx *ctx, void *stream);
+/* Wait for all work the context queued. */
+int polfed_synchronize(polfed_ctx *ctx);
+
+/* ---- host-side helpers (no device work) -------------------------------- */
+
+/* C(L, L/2), the Sz=0 sector size ("Benchmark models"); -1 if L is odd or
+ * outside [2, 30]. */
+long long polfed_dim(int L);
+void polfed_default_opts(polfed_opts *opts);
+
+/* Chebyshev coefficients of eq. (polyTransf): c[n] = sqrt(4 - 3 delta_n0)
+ * cos(n arccos sigma_tilde), n = 0..K (c: host array of K+1), and *D with
+ * P(sigma_tilde) = 1.  |sigma_tilde| < 1. */
+int polfed_cheb_coeffs(double sigma_tilde, long long K, double *c, double *D);
+
+/* Filter order from the density of states (main text "POLFED algorithm",
+ * Supplement "Convergence"): K = max{K : n_P(K) >= nwin}, where n_P is the
+ * number of states of the Gaussian DOS (centre Tr H / N, width Gamma with
+ * Gamma^2 = L (J1^2+J2^2)(2+Delta^2)/16 + sum h_i^2/4) inside the main lobe
+ * {x : P_K(x) >= p} around sigma_tilde, for H~ built with bounds E0w, E1w.
+ * Writes *K and the density rho~(sigma_tilde) (states per unit of H~). */
+int polfed_filter_order(const polfed_model *model, double E0w, double E1w,
+                        double sigma_tilde, int nwin, double p,
+                        long long *K, double *rho);
+
+/* ---- stage calls (device pointers, async on the context stream) -------- */
+
+/* states[r] = the r-th Sz=0 state (uint32, length polfed_dim(L)). */
+int polfed_basis(polfed_ctx *ctx, int L, uint32_t *states);
+/* ranks[i] = row of states[i] in the Sz=0 basis, or -1 if states[i] is not
+ * an L-bit integer with L/2 set bits.  n >= 0 entries. */
+int polfed_rank(polfed_ctx *ctx, int L, long long n, const uint32_t *states,
+                int32_t *ranks);
+/* d[r] = H[r][r] in FP64 (length polfed_dim(L)). */
+int polfed_diag(polfed_ctx *ctx, const polfed_model *model, double *d);
+/* Y = H X (unscaled H), X and Y n x nvec row-major, n = polfed_dim(L);
+ * precision 0: double, 1: float.  X and Y must not overlap. */
+int polfed_apply_h(polfed_ctx *ctx, const polfed_model *model, int precision,
+                   int nvec, const void *X, void *Y);
+/* Y = P^K_sigma(H~) X, with H~ built from E0, E1 (used as given), by the
+ * Clenshaw recurrence (Supplement, "Technical details"); precision 0:
+ * double, 1: float; K >= 0.  X and Y must not overlap. */
+int polfed_apply_filter(polfed_ctx *ctx, const polfed_model *model, double E0,
+                        double E1, double sigma_tilde, long long K,
+                        int precision, int nvec, const void *X, void *Y);
+
+/* Tall-skinny FP64 products on the matrix cores (block Gram-Schmidt and
+ * projection of eqs. (Lan1)-(Lan2) and the Ritz step).  All operands are
+ * device, row-major, with leading dimensions in elements:
+ *   polfed_gram:   C (p x q, ldc) = X^T Y,  X: n x p, Y: n x q
+ *   polfed_update: Y (n x q) = alpha X C + beta Y,  X: n x p, C: p x q
+ * p, q >= 1; polfed_update needs q <= 64.  Results are deterministic. */
+int polfed_gram(polfed_ctx *ctx, long long n, int p, int q, const double *X,
+                long long ldx, const double *Y, long long ldy, double *C,
+                long long ldc);
+int polfed_update(polfed_ctx *ctx, long long n, int p, int q, double alpha,
+                  const double *X, long long ldx, const double *C,
+                  long long ldc, double beta, double *Y, long long ldy);
+
+/* Symmetric eigendecomposition on the device (cyclic Jacobi, FP64):
+ * A (n x n, row-major, symmetric; overwritten) -> w[n] eigenvalues in
+ * ascending order and V (n x n, row-major) with eigenvector i in column i.
+ * Used for T_m and the Rayleigh-Ritz matrix.  1 <= n <= 4096.  Blocks the
+ * host until done (it reads the convergence flag). */
+int polfed_sym_eig(polfed_ctx *ctx, int n, double *A, double *w, double *V);
+
+/* Spectral bounds: `steps` of single-vector FP64 Lanczos on H from a
+ * seeded start vector (main text: E0, E1 from the Lanczos algorithm).
+ * Writes the extreme Ritz values and their residual bounds |beta_k y_k|.
+ * Blocks the host until done. */
+int polfed_bounds(polfed_ctx *ctx, const polfed_model *model, int steps,
+                  unsigned long long seed, double *E0, double *E1,
+                  double *r0, double *r1);
+
+/* ---- tuning and measurement -------------------------------------------- */
+
+/* Launch shape of the fused Chebyshev-step kernel for chains of length L,
+ * block width nvec (power of two, 1..64) and precision (0: FP64, 1: FP32):
+ * threads per workgroup (256 or 1024), 16-byte loads per lane per gathered
+ * row (lpl: 1, 2 or 4), persistent workgroups per compute unit (1..32) and
+ * whether the rank tables are staged in LDS (ignored for L > 26).  Entries
+ * live in the context; without one the library's built-in default is used.
+ * The autotuner (paper_2005_09534_amd/autotune.py) searches this space. */
+int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads,
+                          int lpl, int wg_per_cu, int lds_tables);
+/* Capture each filter application (its K+1 step launches) in a HIP graph
+ * that is replayed for every Lanczos block (on != 0, the default unless the
+ * environment sets POLFED_NO_GRAPH), or launch the steps one by one.  Used
+ * where a step is short (blocks up to 64 MB, K <= 2^17).  Results are
+ * identical either way. */
+int polfed_set_graphs(polfed_ctx *ctx, int on);
+/* Filter counters accumulated by the context since the last reset (or the
+ * start of the last polfed_solve): kernel time of the Chebyshev steps by HIP
+ * events on the context's stream (seconds), step launches, and algorithmic
+ * bytes (each vector element counted once per stream it is read or
+ * written: n [nvec b (streams) + 4 + b] per step, b = 4 or 8).  Any output
+ * pointer may be NULL.  reset != 0 zeroes the counters after reading. */
+int polfed_filter_stats(polfed_ctx *ctx, double *gpu_s, double *launches, double *bytes,
+                        int reset);
+
+/* ---- the solve --------------------------------------------------------- */
+
+/* The nev eigenpairs of H nearest the target.  Outputs are HOST arrays the
+ * caller allocates: evals[nev] ascending (H units); evecs (nullable)
+ * [dim x nev] column-major (eigenvector i contiguous at evecs + i*dim),
+ * each of unit norm with its largest-|.| entry positive (lowest index on
+ * ties); resid[nev] = ||H v - E v||_2.  info nullable.  opts NULL means
+ * defaults.  Returns POLFED_NOT_CONVERGED (with the best nev pairs) when
+ * the Lanczos column cap is reached first.  Blocks until done. */
+int polfed_solve(polfed_ctx *ctx, const polfed_model *model,
+                 const polfed_opts *opts, int nev, double *evals,
+                 double *evecs, double *resid, polfed_info *info);
+
+/* R independent realisations (paper, "Benchmark": disorder averages are
+ * many independent runs) solved together: models[R] may mix L.  evals and
+ * resid are [R x nev] (realisation-major); evecs NULL or the concatenation
+ * of the per-realisation [dim_r x nev] column-major blocks; infos (nullable)
+ * [R]; status[R] per realisation.  Returns the worst status. */
+int polfed_solve_batch(polfed_ctx *ctx, int R, const polfed_model *models,
+                       const polfed_opts *opts, int nev, double *evals,
+                       double *evecs, double *resid, polfed_info *infos,
+                       int *status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLFED_H */

@@ -102,3 +102,25 @@ def hamiltonian_csr(L, J1, J2, Delta, h):
 def apply_h(H, X):
     """Y = H X for an (n x s) block (plain sparse product)."""
     return H @ X
+
+
+def hamiltonian_row(L, J1, J2, Delta, h, s):
+    """Row of H for one basis state s, by the literal sum of eq. (XXZ):
+    returns {state': value} (the diagonal under s itself).  For sampled
+    checks at sizes where the full CSR is too large."""
+    s = int(s)
+    J = {1: J1, 2: J2}
+    out = {}
+    d = 0.0
+    for l, i, j in _bonds(L):
+        if J[l] == 0.0:
+            continue
+        si, sj = (s >> i) & 1, (s >> j) & 1
+        d += J[l] * Delta * (si - 0.5) * (sj - 0.5)
+        if si != sj:
+            t = s ^ ((1 << i) | (1 << j))
+            out[t] = out.get(t, 0.0) + 0.5 * J[l]
+    for i in range(L):
+        d += h[i] * (((s >> i) & 1) - 0.5)
+    out[s] = out.get(s, 0.0) + d
+    return out

@@ -1,0 +1,167 @@
+// Sz=0 basis of the spin chain: enumeration, ranking and the diagonal of H.
+//
+// The sector of zero magnetisation holds the C(L, L/2) L-bit integers with
+// L/2 set bits (paper, "Benchmark models").  Row r is the r-th such integer
+// in ascending order; ascending order of fixed-weight bit strings is the
+// colexicographic order of their set-bit positions p_1 < ... < p_{L/2}, whose
+// rank is sum_t C(p_t, t).  Unranking inverts that sum greedily from the top
+// bit.  Ranking uses two tables split at bit `half` = L/2: the low half
+// contributes sum over its own set bits, and the high half's bits have
+// known index t = (L/2 - popcount(hi)) + u, so each half's term is a table
+// lookup and rank(s) = tabA[hi] + tabB[lo].
+#include "internal.h"
+
+namespace polfed {
+
+__constant__ uint32_t c_binom[33][33];  // C(n, k), n, k <= 32 (C(32,16) < 2^32)
+
+void upload_binomials(int device) {
+  static bool done[64] = {false};
+  if (device >= 0 && device < 64 && done[device]) return;
+  uint32_t tab[33][33];
+  for (int n = 0; n <= 32; ++n)
+    for (int k = 0; k <= 32; ++k) {
+      if (k > n) tab[n][k] = 0;
+      else if (k == 0 || k == n) tab[n][k] = 1;
+      else tab[n][k] = tab[n - 1][k - 1] + tab[n - 1][k];
+    }
+  PF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_binom), tab, sizeof(tab)));
+  if (device >= 0 && device < 64) done[device] = true;
+}
+
+__global__ void k_unrank(uint32_t *states, long long n, int L) {
+  long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  uint32_t rem = (uint32_t)r;
+  uint32_t s = 0;
+  int p = L - 1;
+  for (int t = L / 2; t >= 1; --t) {
+    while (c_binom[p][t] > rem) --p;  // stops at p >= t-1, where C(p,t) = 0
+    s |= 1u << p;
+    rem -= c_binom[p][t];
+    --p;
+  }
+  states[r] = s;
+}
+
+// tabB[lo] = sum over set bits q (ascending, index t = 1, 2, ...) of C(q, t)
+// tabA[hi] = sum over set bits q of hi (index t continuing after the
+//            L/2 - popcount(hi) bits below) of C(half + q, t)
+__global__ void k_rank_tables(int32_t *tabA, int32_t *tabB, int L, int half) {
+  int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (1 << half)) return;
+  int t = 0;
+  uint32_t sb = 0;
+  for (int q = 0; q < half; ++q)
+    if ((x >> q) & 1) sb += c_binom[q][++t];
+  tabB[x] = (int32_t)sb;
+  int below = L / 2 - __popc((uint32_t)x);
+  uint32_t sa = 0;
+  if (below >= 0) {
+    t = below;
+    for (int q = 0; q < L - half; ++q)
+      if ((x >> q) & 1) sa += c_binom[half + q][++t];
+  }
+  tabA[x] = (int32_t)sa;
+}
+
+__global__ void k_rank(const uint32_t *states, int32_t *ranks, long long n, const int32_t *tabA,
+                       const int32_t *tabB, int L, int half) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t s = states[i];
+  bool ok = (L >= 32 || (s >> L) == 0) && __popc(s) == L / 2;
+  ranks[i] = ok ? tabA[s >> half] + tabB[s & ((1u << half) - 1u)] : -1;
+}
+
+void build_basis(hipStream_t st, Basis &b, int L) {
+  b.L = L;
+  b.half = L / 2;
+  b.n = polfed_dim(L);
+  b.states.ensure(sizeof(uint32_t) * b.n);
+  b.tabA.ensure(sizeof(int32_t) << b.half);
+  b.tabB.ensure(sizeof(int32_t) << b.half);
+  int th = 256;
+  k_unrank<<<(unsigned)((b.n + th - 1) / th), th, 0, st>>>(b.states.as<uint32_t>(), b.n, L);
+  check_launch("k_unrank");
+  k_rank_tables<<<(unsigned)(((1 << b.half) + th - 1) / th), th, 0, st>>>(
+      b.tabA.as<int32_t>(), b.tabB.as<int32_t>(), L, b.half);
+  check_launch("k_rank_tables");
+}
+
+void launch_rank(hipStream_t st, const Basis &b, long long n, const uint32_t *states,
+                 int32_t *ranks) {
+  if (n <= 0) return;
+  int th = 256;
+  k_rank<<<(unsigned)((n + th - 1) / th), th, 0, st>>>(states, ranks, n, b.tabA.as<int32_t>(),
+                                                      b.tabB.as<int32_t>(), b.L, b.half);
+  check_launch("k_rank");
+}
+
+struct DiagArgs {
+  double h[32];
+  double J1, J2, Delta;
+  int L;
+};
+
+// H[r][r] = sum_l (J_l Delta / 4) (L - 2 popcount(s ^ rot_l(s)))
+//           + sum_{i set} h_i - (1/2) sum_i h_i
+// where bit i of s ^ rot_l(s) marks an antiparallel bond (i, i+l mod L);
+// each bond contributes +1/4 (parallel) or -1/4 (antiparallel) times J_l
+// Delta, and the field term is h_i S^z_i with S^z = n_i - 1/2.
+__global__ void k_diag(const uint32_t *states, double *d, long long n, DiagArgs a) {
+  long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  uint32_t s = states[r];
+  int L = a.L;
+  uint32_t mask = (L >= 32) ? 0xffffffffu : ((1u << L) - 1u);
+  uint32_t rot1 = ((s >> 1) | (s << (L - 1))) & mask;
+  int anti1 = __popc(s ^ rot1);
+  double v = 0.25 * a.J1 * a.Delta * (double)(L - 2 * anti1);
+  if (a.J2 != 0.0) {
+    uint32_t rot2 = ((s >> 2) | (s << (L - 2))) & mask;
+    int anti2 = __popc(s ^ rot2);
+    v += 0.25 * a.J2 * a.Delta * (double)(L - 2 * anti2);
+  }
+  double hs = 0.0, htot = 0.0;
+  for (int i = 0; i < L; ++i) {
+    htot += a.h[i];
+    if ((s >> i) & 1u) hs += a.h[i];
+  }
+  d[r] = v + hs - 0.5 * htot;
+}
+
+void launch_diag(hipStream_t st, const Chain &c, double *d) {
+  DiagArgs a;
+  for (int i = 0; i < 32; ++i) a.h[i] = (i < c.L) ? c.h[i] : 0.0;
+  a.J1 = c.J1;
+  a.J2 = c.J2;
+  a.Delta = c.Delta;
+  a.L = c.L;
+  long long n = c.basis->n;
+  int th = 256;
+  k_diag<<<(unsigned)((n + th - 1) / th), th, 0, st>>>(c.basis->states.as<uint32_t>(), d, n, a);
+  check_launch("k_diag");
+}
+
+// dt[r] = a d[r] + b, rounded to T: the diagonal of H~ = aH + b.
+template <class T>
+__global__ void k_scaled_diag(long long n, const double *d, double a, double b, T *out) {
+  long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] = (T)(a * d[r] + b);
+}
+
+template <class T>
+void launch_scaled_diag(hipStream_t st, long long n, const double *d, double a, double b,
+                        T *out) {
+  int th = 256;
+  k_scaled_diag<T><<<(unsigned)((n + th - 1) / th), th, 0, st>>>(n, d, a, b, out);
+  check_launch("k_scaled_diag");
+}
+
+template void launch_scaled_diag<float>(hipStream_t, long long, const double *, double, double,
+                                        float *);
+template void launch_scaled_diag<double>(hipStream_t, long long, const double *, double, double,
+                                         double *);
+
+}  // namespace polfed

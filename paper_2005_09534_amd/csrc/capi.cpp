@@ -1,0 +1,389 @@
+// C-ABI entry points of libpolfed (declared in include/polfed.h).
+//
+// Every entry point converts internal exceptions into a status code and
+// records the message on the context; nothing throws across the ABI.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "internal.h"
+
+namespace polfed {
+
+void make_chain(polfed_ctx *ctx, const polfed_model *m, Chain &c);
+int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opts, int nev,
+              double *evals, double *evecs, double *resid, polfed_info *info);
+void run_bounds(polfed_ctx *ctx, const Chain &c, int steps, unsigned long long seed, double &E0,
+                double &E1, double &r0, double &r1);
+template <class T>
+void stage_apply_h(polfed_ctx *ctx, const Chain &c, int nvec, const T *X, T *Y);
+template <class T>
+void stage_apply_filter(polfed_ctx *ctx, const Chain &c, double E0, double E1, double sigma,
+                        long long K, int nvec, const T *X, T *Y);
+
+void check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    throw Error(POLFED_EDEVICE, std::string("launch of ") + what + ": " + hipGetErrorString(e));
+}
+
+DevBuf::~DevBuf() {
+  if (p) (void)hipFree(p);
+}
+
+void *DevBuf::ensure(size_t nbytes) {
+  if (nbytes == 0) nbytes = 1;
+  if (nbytes <= bytes) return p;
+  if (p) {
+    // queued kernels may still use the old block
+    PF_HIP(hipDeviceSynchronize());
+    PF_HIP(hipFree(p));
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw Error(POLFED_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
+  }
+  bytes = nbytes;
+  return p;
+}
+
+static bool pow2_block(int s) { return s >= 1 && s <= 64 && (s & (s - 1)) == 0; }
+
+template <class F>
+static int guarded(polfed_ctx *ctx, F &&f) {
+  if (!ctx) return POLFED_EINVAL;
+  try {
+    PF_HIP(hipSetDevice(ctx->device));
+    ctx->last_error.clear();
+    return f();
+  } catch (const Error &e) {
+    ctx->last_error = e.what();
+    return e.code;
+  } catch (const std::exception &e) {
+    ctx->last_error = e.what();
+    return POLFED_EDEVICE;
+  }
+}
+
+}  // namespace polfed
+
+using namespace polfed;
+
+const Basis &polfed_ctx::basis(int L) {
+  auto &p = bases[L];
+  if (!p) {
+    p.reset(new Basis());
+    build_basis(stream, *p, L);
+  }
+  return *p;
+}
+
+extern "C" {
+
+long long polfed_dim(int L) {
+  if (L < 2 || L > 30 || (L & 1)) return -1;
+  long long r = 1;
+  for (int k = 1; k <= L / 2; ++k) r = r * (L / 2 + k) / k;
+  return r;
+}
+
+void polfed_default_opts(polfed_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->target_kind = 0;
+  o->target = 0.5;
+  o->block_size = 0;
+  o->K = 0;
+  o->p = 0.17;
+  o->precision = 0;
+  o->window_factor = 1.5;
+  o->max_cols = 0;
+  o->tol = 1e-10;
+  o->eta = 1e-3;
+  o->bounds_steps = 200;
+  o->seed = 12345;
+}
+
+int polfed_create(int device, polfed_ctx **out) {
+  if (!out) return POLFED_EINVAL;
+  *out = nullptr;
+  polfed_ctx *ctx = new polfed_ctx();
+  ctx->device = device;
+  try {
+    int ndev = 0;
+    PF_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) {
+      delete ctx;
+      return POLFED_EINVAL;
+    }
+    PF_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    PF_HIP(hipGetDeviceProperties(&prop, device));
+    ctx->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    PF_HIP(hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
+    ctx->stream = ctx->own_stream;
+    ctx->use_graphs = std::getenv("POLFED_NO_GRAPH") ? 0 : 1;
+    upload_binomials(device);
+  } catch (const Error &e) {
+    delete ctx;
+    return e.code;
+  }
+  *out = ctx;
+  return POLFED_OK;
+}
+
+int polfed_destroy(polfed_ctx *ctx) {
+  if (!ctx) return POLFED_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->bases.clear();
+  ctx->bufs.clear();
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+  if (ctx->filter_graph) (void)hipGraphExecDestroy(ctx->filter_graph);
+  if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
+  if (ctx->ev_stop) (void)hipEventDestroy(ctx->ev_stop);
+  delete ctx;
+  return POLFED_OK;
+}
+
+const char *polfed_last_error(const polfed_ctx *ctx) {
+  return ctx ? ctx->last_error.c_str() : "null context";
+}
+
+int polfed_set_stream(polfed_ctx *ctx, void *stream) {
+  return guarded(ctx, [&] {
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return POLFED_OK;
+  });
+}
+
+int polfed_synchronize(polfed_ctx *ctx) {
+  return guarded(ctx, [&] {
+    PF_HIP(hipStreamSynchronize(ctx->stream));
+    return POLFED_OK;
+  });
+}
+
+int polfed_cheb_coeffs(double sigma, long long K, double *c, double *D) {
+  if (!c || !D || K < 0 || !(std::fabs(sigma) < 1.0)) return POLFED_EINVAL;
+  std::vector<double> v;
+  double d;
+  cheb_coeffs(sigma, K, v, d);
+  std::memcpy(c, v.data(), sizeof(double) * (size_t)(K + 1));
+  *D = d;
+  return POLFED_OK;
+}
+
+int polfed_filter_order(const polfed_model *m, double E0w, double E1w, double sigma, int nwin,
+                        double p, long long *K, double *rho) {
+  if (!m || !m->h || !K || nwin < 1 || !(E1w > E0w) || !(std::fabs(sigma) < 1.0) || !(p > 0.0))
+    return POLFED_EINVAL;
+  long long n = polfed_dim(m->L);
+  if (n < 0) return POLFED_EINVAL;
+  const double Gamma = dos_gamma(m->L, m->J1, m->J2, m->Delta, m->h);
+  const double Ebar = trace_mean(m->L, m->J1, m->J2, m->Delta);
+  double r = 0.0;
+  *K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, p, &r);
+  if (rho) *rho = r;
+  return POLFED_OK;
+}
+
+int polfed_basis(polfed_ctx *ctx, int L, uint32_t *states) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(polfed_dim(L) > 0 && L >= 2, "L must be even in [2, 30]");
+    PF_REQUIRE(states != nullptr, "states is NULL");
+    const Basis &b = ctx->basis(L);
+    PF_HIP(hipMemcpyAsync(states, b.states.p, sizeof(uint32_t) * b.n, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    return POLFED_OK;
+  });
+}
+
+int polfed_rank(polfed_ctx *ctx, int L, long long n, const uint32_t *states, int32_t *ranks) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(polfed_dim(L) > 0 && L >= 2, "L must be even in [2, 30]");
+    PF_REQUIRE(n >= 0, "n must be >= 0");
+    PF_REQUIRE(n == 0 || (states && ranks), "states/ranks NULL");
+    launch_rank(ctx->stream, ctx->basis(L), n, states, ranks);
+    return POLFED_OK;
+  });
+}
+
+int polfed_diag(polfed_ctx *ctx, const polfed_model *m, double *d) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(d != nullptr, "d is NULL");
+    Chain c;
+    make_chain(ctx, m, c);
+    PF_HIP(hipMemcpyAsync(d, c.diag.p, sizeof(double) * c.basis->n, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    PF_HIP(hipStreamSynchronize(ctx->stream));  // c.diag is freed on return
+    return POLFED_OK;
+  });
+}
+
+int polfed_apply_h(polfed_ctx *ctx, const polfed_model *m, int precision, int nvec, const void *X,
+                   void *Y) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
+    PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
+    PF_REQUIRE(X && Y && X != Y, "X, Y must be distinct non-NULL device pointers");
+    Chain c;
+    make_chain(ctx, m, c);
+    if (precision == 0)
+      stage_apply_h<double>(ctx, c, nvec, static_cast<const double *>(X), static_cast<double *>(Y));
+    else
+      stage_apply_h<float>(ctx, c, nvec, static_cast<const float *>(X), static_cast<float *>(Y));
+    PF_HIP(hipStreamSynchronize(ctx->stream));
+    return POLFED_OK;
+  });
+}
+
+int polfed_apply_filter(polfed_ctx *ctx, const polfed_model *m, double E0, double E1,
+                        double sigma, long long K, int precision, int nvec, const void *X,
+                        void *Y) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
+    PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
+    PF_REQUIRE(X && Y && X != Y, "X, Y must be distinct non-NULL device pointers");
+    PF_REQUIRE(E1 > E0, "E1 must exceed E0");
+    PF_REQUIRE(std::fabs(sigma) < 1.0, "|sigma_tilde| must be < 1");
+    PF_REQUIRE(K >= 0 && K <= (1LL << 26), "K must be in [0, 2^26]");
+    Chain c;
+    make_chain(ctx, m, c);
+    if (precision == 0)
+      stage_apply_filter<double>(ctx, c, E0, E1, sigma, K, nvec, static_cast<const double *>(X),
+                                 static_cast<double *>(Y));
+    else
+      stage_apply_filter<float>(ctx, c, E0, E1, sigma, K, nvec, static_cast<const float *>(X),
+                                static_cast<float *>(Y));
+    PF_HIP(hipStreamSynchronize(ctx->stream));
+    return POLFED_OK;
+  });
+}
+
+int polfed_gram(polfed_ctx *ctx, long long n, int p, int q, const double *X, long long ldx,
+                const double *Y, long long ldy, double *C, long long ldc) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(n >= 0 && p >= 1 && q >= 1, "need n >= 0, p, q >= 1");
+    PF_REQUIRE(ldx >= p && ldy >= q && ldc >= q, "leading dimensions too small");
+    PF_REQUIRE(X && Y && C, "NULL operand");
+    if (n == 0) {
+      for (int i = 0; i < p; ++i)
+        PF_HIP(hipMemsetAsync(C + (size_t)i * ldc, 0, sizeof(double) * q, ctx->stream));
+      return POLFED_OK;
+    }
+    launch_gram(ctx->stream, n, p, q, X, ldx, Y, ldy, C, ldc, ctx->buf("partials"), ctx->num_cu);
+    return POLFED_OK;
+  });
+}
+
+int polfed_update(polfed_ctx *ctx, long long n, int p, int q, double alpha, const double *X,
+                  long long ldx, const double *C, long long ldc, double beta, double *Y,
+                  long long ldy) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(n >= 0 && p >= 1 && q >= 1 && q <= 64, "need n >= 0, p >= 1, 1 <= q <= 64");
+    PF_REQUIRE(ldx >= p && ldc >= q && ldy >= q, "leading dimensions too small");
+    PF_REQUIRE(X && C && Y, "NULL operand");
+    launch_update(ctx->stream, n, p, q, alpha, X, ldx, C, ldc, beta, Y, ldy);
+    return POLFED_OK;
+  });
+}
+
+int polfed_sym_eig(polfed_ctx *ctx, int n, double *A, double *w, double *V) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(n >= 1 && n <= 4096, "n must be in [1, 4096]");
+    PF_REQUIRE(A && w && V, "NULL operand");
+    sym_eig(ctx->stream, n, A, w, V, ctx->buf("eigwork"));
+    PF_HIP(hipStreamSynchronize(ctx->stream));
+    return POLFED_OK;
+  });
+}
+
+int polfed_bounds(polfed_ctx *ctx, const polfed_model *m, int steps, unsigned long long seed,
+                  double *E0, double *E1, double *r0, double *r1) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(steps >= 1, "steps must be >= 1");
+    PF_REQUIRE(E0 && E1, "NULL output");
+    Chain c;
+    make_chain(ctx, m, c);
+    double a, b, ra, rb;
+    run_bounds(ctx, c, steps, seed, a, b, ra, rb);
+    *E0 = a;
+    *E1 = b;
+    if (r0) *r0 = ra;
+    if (r1) *r1 = rb;
+    return POLFED_OK;
+  });
+}
+
+int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads, int lpl,
+                          int wg_per_cu, int lds_tables) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
+    PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
+    PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
+    PF_REQUIRE(threads == 256 || threads == 1024, "threads must be 256 or 1024");
+    PF_REQUIRE(lpl == 1 || lpl == 2 || lpl == 4, "lpl must be 1, 2 or 4");
+    PF_REQUIRE(wg_per_cu >= 1 && wg_per_cu <= 32, "wg_per_cu must be in [1, 32]");
+    StepShape sh;
+    sh.threads = threads;
+    sh.lpl = lpl;
+    sh.wg_per_cu = wg_per_cu;
+    sh.lds_tables = lds_tables ? 1 : 0;
+    ctx->shapes[std::make_tuple(L, nvec, precision ? 4 : 8)] = sh;
+    return POLFED_OK;
+  });
+}
+
+int polfed_set_graphs(polfed_ctx *ctx, int on) {
+  return guarded(ctx, [&] {
+    ctx->use_graphs = on ? 1 : 0;
+    return POLFED_OK;
+  });
+}
+
+int polfed_filter_stats(polfed_ctx *ctx, double *gpu_s, double *launches, double *bytes,
+                        int reset) {
+  return guarded(ctx, [&] {
+    if (gpu_s) *gpu_s = ctx->filter_gpu_s;
+    if (launches) *launches = ctx->filter_launches;
+    if (bytes) *bytes = ctx->filter_bytes;
+    if (reset) {
+      ctx->filter_gpu_s = 0.0;
+      ctx->filter_launches = 0.0;
+      ctx->filter_bytes = 0.0;
+    }
+    return POLFED_OK;
+  });
+}
+
+int polfed_solve(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opts, int nev,
+                 double *evals, double *evecs, double *resid, polfed_info *info) {
+  return guarded(ctx, [&] { return solve_one(ctx, model, opts, nev, evals, evecs, resid, info); });
+}
+
+int polfed_solve_batch(polfed_ctx *ctx, int R, const polfed_model *models,
+                       const polfed_opts *opts, int nev, double *evals, double *evecs,
+                       double *resid, polfed_info *infos, int *status) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(R >= 1 && models && status && evals && resid, "invalid batch arguments");
+    int worst = POLFED_OK;
+    size_t off = 0;
+    for (int r = 0; r < R; ++r) {
+      int rc = solve_one(ctx, &models[r], opts, nev, evals + (size_t)r * nev,
+                         evecs ? evecs + off : nullptr, resid + (size_t)r * nev,
+                         infos ? infos + r : nullptr);
+      status[r] = rc;
+      if (rc < 0 && worst >= 0) worst = rc;
+      if (rc > 0 && worst == POLFED_OK) worst = rc;
+      off += (size_t)polfed_dim(models[r].L) * nev;
+    }
+    return worst;
+  });
+}
+
+}  // extern "C"

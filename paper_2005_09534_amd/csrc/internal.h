@@ -1,0 +1,240 @@
+// Internal declarations of libpolfed (host C++ and HIP device code).
+// Not part of the ABI; the public contract is include/polfed.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <tuple>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/polfed.h"
+
+namespace polfed {
+
+// ---------------------------------------------------------------- errors --
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define PF_HIP(expr)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::polfed::Error(POLFED_EDEVICE, std::string(#expr) + ": " +       \
+                                                hipGetErrorString(e_));       \
+  } while (0)
+
+#define PF_REQUIRE(cond, msg)                                                 \
+  do {                                                                        \
+    if (!(cond)) throw ::polfed::Error(POLFED_EINVAL, (msg));                 \
+  } while (0)
+
+// Check the launch that was just queued.
+void check_launch(const char *what);
+
+// ----------------------------------------------------------- device memory --
+
+// Owning device buffer (hipMalloc / hipFree); grows on demand.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf();
+  void *ensure(size_t nbytes);  // contents not preserved on growth
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ------------------------------------------------------- chain on the GPU --
+
+// Device-resident description of the Sz=0 basis of one chain length L:
+// states[n] ascending, and the two rank tables with
+//   rank(s) = tabA[s >> half] + tabB[s & (2^half - 1)]
+// (the colexicographic rank sum_t C(p_t, t) split at bit `half`; each half
+// contributes a term that depends only on its own bits once the total
+// popcount is fixed at L/2).
+struct Basis {
+  int L = 0;
+  int half = 0;
+  long long n = 0;
+  DevBuf states, tabA, tabB;
+};
+
+// One chain (model + basis + diagonal in FP64).
+struct Chain {
+  int L;
+  double J1, J2, Delta;
+  double h[32];
+  const Basis *basis;
+  DevBuf diag;  // FP64 H[r][r]
+};
+
+// Maximum L handled with the rank tables in LDS (2 * 2^(L/2) int32).
+constexpr int kMaxLdsTableL = 26;
+
+// --------------------------------------------------------------- kernels --
+
+// basis.hip
+void upload_binomials(int device);
+void build_basis(hipStream_t st, Basis &b, int L);
+void launch_rank(hipStream_t st, const Basis &b, long long n, const uint32_t *states,
+                 int32_t *ranks);
+void launch_diag(hipStream_t st, const Chain &c, double *d);
+template <class T>
+void launch_scaled_diag(hipStream_t st, long long n, const double *d, double a, double b, T *out);
+
+// hv.hip: the fused Chebyshev step / H~ application
+//   out[r,:] = alpha X[r,:] + dscale dt[r] V[r,:] + sum_bonds w_l V[nbr,:]
+//              + gamma W[r,:]
+// X, W may be null (alpha / gamma ignored); V may be null (no operator
+// term).  Rows are row-major with the given leading dimensions.
+template <class T>
+struct StepArgs {
+  const uint32_t *states;
+  const T *dt;
+  const int32_t *tabA;
+  const int32_t *tabB;
+  const T *X;
+  long long ldx;
+  const T *V;
+  long long ldv;
+  const T *W;
+  long long ldw;
+  T *out;
+  long long ldo;
+  T alpha, dscale, w1, w2, gamma;
+  long long n;
+  int L, half;
+  uint32_t lomask, fullmask;
+  int has_j2;
+  long long rows_per_wg;
+};
+
+// Launch shape of the step kernel (the autotuner's search space).
+struct StepShape {
+  int threads = 256;     // workgroup size (multiple of 64)
+  int lpl = 1;           // 16-byte loads per lane per gathered row
+  int wg_per_cu = 8;     // persistent workgroups per CU
+  int lds_tables = 1;    // stage rank tables in LDS
+};
+
+template <class T>
+void launch_step(hipStream_t st, int S, const StepArgs<T> &a, const StepShape &shape, int num_cu);
+// Built-in default shape (used when the context holds no tuned entry).
+StepShape default_shape(int L, int S, bool fp32);
+
+template <class Tin, class Tout>
+void launch_cast(hipStream_t st, long long n, int S, const Tin *in, long long ldin, Tout *out,
+                 long long ldout);
+
+// dense.hip: FP64 tall-skinny products and small dense kernels
+void launch_gram(hipStream_t st, long long n, int p, int q, const double *X, long long ldx,
+                 const double *Y, long long ldy, double *C, long long ldc, DevBuf &partials,
+                 int num_cu);
+void launch_update(hipStream_t st, long long n, int p, int q, double alpha, const double *X,
+                   long long ldx, const double *C, long long ldc, double beta, double *Y,
+                   long long ldy);
+// Jacobi eigensolver; A (n x n) overwritten; w ascending, V columns.
+void sym_eig(hipStream_t st, int n, double *A, double *w, double *V, DevBuf &work);
+// Cholesky of the s x s Gram matrix G (device, row-major, ld s):
+// writes Rinv = L^{-T} (upper) and B = L^T (upper), and flag[0] = index+1
+// of the first non-positive pivot (0 if fine).
+void launch_chol(hipStream_t st, int s, const double *G, double *Rinv, double *B, int *flag,
+                 double rel_tol);
+// C = A * B for small row-major matrices (device), C: m x k, A: m x l, B: l x k.
+void launch_small_gemm(hipStream_t st, int m, int l, int k, const double *A, int lda,
+                       const double *B, int ldb, double *C, int ldc, int transA);
+// Fill X (n x S, ld) with uniform [-1,1) from Philox4x32-10 keyed by seed,
+// counter (row, col, stream).
+void launch_philox_fill(hipStream_t st, long long n, int S, double *X, long long ld,
+                        unsigned long long seed, unsigned stream_id);
+// Column 2-norms of X (n x q): out[q] (two-stage, deterministic).
+void launch_colnorms(hipStream_t st, long long n, int q, const double *X, long long ldx,
+                     double *out, DevBuf &partials, int num_cu);
+// Residual norms ||HV - V diag(E)|| columns: HV, V (n x q), E[q] -> out[q].
+void launch_resid_norms(hipStream_t st, long long n, int q, const double *HV, long long ldhv,
+                        const double *V, long long ldv, const double *E, double *out,
+                        DevBuf &partials, int num_cu);
+// Scale columns: X[:, j] *= f[j].
+void launch_scale_cols(hipStream_t st, long long n, int q, double *X, long long ldx,
+                       const double *f);
+// Sign normalisation factors: f[j] = sign of the largest-|.| entry of
+// column j (lowest row on ties).
+void launch_sign_factors(hipStream_t st, long long n, int q, const double *X, long long ldx,
+                         double *f, DevBuf &partials, int num_cu);
+// Transpose row-major X (n x q) into column-major out (out[j*n + r]).
+void launch_to_colmajor(hipStream_t st, long long n, int q, const double *X, long long ldx,
+                        double *out);
+// Gather columns: out[:, j] = X[:, idx[j]].
+void launch_gather_cols(hipStream_t st, long long n, int q, const double *X, long long ldx,
+                        const int *idx, double *out, long long ldo);
+void launch_fill(hipStream_t st, double *x, long long count, double v);
+void launch_small_transpose(hipStream_t st, int m, int k, const double *in, int ldi, double *out,
+                            int ldo);
+void launch_symmetrize(hipStream_t st, int s, double *A, int lda);
+
+// Bounds Lanczos helpers (single vector, FP64, scalars on device).
+void launch_dot_partials(hipStream_t st, long long n, const double *x, const double *y,
+                         double *part, int nblk);
+void launch_lanczos_update(hipStream_t st, long long n, double *w, const double *v,
+                           const double *vprev, const double *part, int nblk, double *alpha,
+                           const double *beta_prev, double *part2);
+void launch_lanczos_normalize(hipStream_t st, long long n, const double *w, double *vnext,
+                              const double *part2, int nblk, double *beta);
+
+// ------------------------------------------------------------ host math --
+
+// plan.cpp
+void cheb_coeffs(double sigma, long long K, std::vector<double> &c, double &D);
+double dos_gamma(int L, double J1, double J2, double Delta, const double *h);
+double trace_mean(int L, double J1, double J2, double Delta);
+long long choose_order(long long N, double Ebar, double Gamma, double E0w, double E1w,
+                       double sigma, int nwin, double p, double *rho);
+// Extreme eigenvalues of the symmetric tridiagonal (alpha[k], beta[k] for
+// k=1..k-1 off-diagonal) and the last components of their unit
+// eigenvectors.
+void tridiag_extremes(const std::vector<double> &alpha, const std::vector<double> &beta,
+                      double &lo, double &hi, double &ylo_last, double &yhi_last);
+
+}  // namespace polfed
+
+// ---------------------------------------------------------------- context --
+
+struct polfed_ctx {
+  int device = 0;
+  int num_cu = 256;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  std::map<int, std::unique_ptr<polfed::Basis>> bases;  // per L
+  std::map<std::string, std::unique_ptr<polfed::DevBuf>> bufs;
+  // HIP-event timing of the filter kernels (Chebyshev steps), accumulated
+  // over a solve: GPU seconds between the first and last step of each
+  // filter application, and the number of step launches
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+  double filter_gpu_s = 0.0;
+  double filter_launches = 0.0;
+  double filter_bytes = 0.0;
+  // launch shapes of the step kernel chosen by the autotuner, keyed by
+  // (L, block width, precision bytes)
+  std::map<std::tuple<int, int, int>, polfed::StepShape> shapes;
+  // cached HIP graph of one whole filter application (K+1 step launches),
+  // replayed for every Lanczos block; keyed by everything baked into it
+  hipGraphExec_t filter_graph = nullptr;
+  std::vector<unsigned long long> filter_graph_key;
+  int use_graphs = 1;
+  polfed::DevBuf &buf(const std::string &name) {
+    auto &p = bufs[name];
+    if (!p) p.reset(new polfed::DevBuf());
+    return *p;
+  }
+  const polfed::Basis &basis(int L);
+};

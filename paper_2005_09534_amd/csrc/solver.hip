@@ -1,0 +1,887 @@
+// POLFED solve on one GPU: host control loop around the device kernels.
+//
+// Steps (main text, "POLFED algorithm"; Supplement, "Convergence of POLFED"):
+//  1. Lanczos on H for the extremes E0, E1, widened by their residual bound
+//     and a margin eta (E1 - E0): a Chebyshev series of order K grows like
+//     cosh(K sqrt(2 delta)) at a distance delta outside [-1, 1].
+//  2. H~ = a H + b; target sigma~ = a sigma_H + b.
+//  3. K from the density of states for a window of N_win = ceil(f N_ev)
+//     eigenvalues (f = 1.5 by default: the Gaussian estimate can exceed the
+//     local density, and K ~ 1/N_win keeps the filter work unchanged).
+//  4. Q_1: Philox start block, orthonormalised.
+//  5. Block Lanczos on P(H~), eqs. (Lan1)-(Lan2):
+//        U = P Q_j - Q_{j-1} B_j^T ; A_j = sym(Q_j^T U) ; U -= Q_j A_j ;
+//        U -= Qm (Qm^T U) twice (full reorthogonalisation, not fed into T) ;
+//        Q_{j+1} B_{j+1} = U by CholeskyQR2 (diag(B) > 0).
+//     T_m is block tridiagonal with A_j, B_{j+1} below and B_{j+1}^T above.
+//  6. Eigenpairs (theta_i, t_i) of T_m; converged when theta_i >= p and
+//     ||B_{j+1} t~_i|| <= tau; stop once N_ev have converged.
+//  7. Ritz vectors Qm t_i for theta_i >= p; Rayleigh-Ritz of H~ on their span
+//     (eps_i = u_i^T H~ u_i when the theta_i are distinct; P is even around
+//     sigma locally, so pairs sigma +- d share theta and need the joint
+//     projection); the N_ev values nearest sigma; residuals ||Hv - Ev||.
+// In FP32 mode the filter runs in FP32 (X and the recurrence vectors), and
+// everything else in FP64; a refinement in FP64 follows (see refine()).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <cstdint>
+#include <numeric>
+
+#include "internal.h"
+
+namespace polfed {
+
+static double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------ operators --
+
+// Step arguments for a chain with the given diagonal (in T) and weights.
+template <class T>
+static StepArgs<T> base_args(const Chain &c, const T *dt) {
+  StepArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  const Basis &b = *c.basis;
+  a.states = b.states.as<uint32_t>();
+  a.dt = dt;
+  a.tabA = b.tabA.as<int32_t>();
+  a.tabB = b.tabB.as<int32_t>();
+  a.n = b.n;
+  a.L = c.L;
+  a.half = b.half;
+  a.lomask = (1u << b.half) - 1u;
+  a.fullmask = (c.L >= 32) ? 0xffffffffu : ((1u << c.L) - 1u);
+  a.has_j2 = (c.J2 != 0.0) ? 1 : 0;
+  return a;
+}
+
+static StepShape shape_for(const polfed_ctx *ctx, int L, int S, bool fp32) {
+  auto it = ctx->shapes.find(std::make_tuple(L, S, fp32 ? 4 : 8));
+  if (it != ctx->shapes.end()) return it->second;
+  return default_shape(L, S, fp32);
+}
+
+// out = scale * (dt .* V + sum w_l V[nbr]) for a block of `width` columns,
+// split into power-of-two chunks of at most 64 columns.
+template <class T>
+static void apply_op(polfed_ctx *ctx, const Chain &c, const T *dt, double wscale1,
+                     double wscale2, const T *V, long long ldv, T *out, long long ldo, int width,
+                     bool fp32) {
+  int off = 0;
+  while (off < width) {
+    int S = 64;
+    while (S > width - off) S >>= 1;
+    StepArgs<T> a = base_args<T>(c, dt);
+    a.V = V + off;
+    a.ldv = ldv;
+    a.out = out + off;
+    a.ldo = ldo;
+    a.dscale = T(1);
+    a.w1 = (T)wscale1;
+    a.w2 = (T)wscale2;
+    launch_step<T>(ctx->stream, S, a, shape_for(ctx, c.L, S, fp32), ctx->num_cu);
+    off += S;
+  }
+}
+
+// Y = P^K_sigma(H~) X by Clenshaw:  b_k = c_k X + 2 H~ b_{k+1} - b_{k+2},
+// k = K..1, then Y = (c_0 X + H~ b_1 - b_2) / D.  dt = a d + b in T.
+// Returns the algorithmic bytes of the launches it queues.
+template <class T>
+static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shape, const Chain &c,
+                           const T *dt, double a, int S, const T *X, long long ldx, T *Y,
+                           long long ldy, long long K, const std::vector<double> &coef, double D,
+                           T *buf3) {
+  const long long n = c.basis->n;
+  T *bufs[3] = {buf3, buf3 + (size_t)n * S, buf3 + (size_t)2 * n * S};
+  const double bpv = sizeof(T);
+  double moved = 0.0;
+  for (long long j = 0; j < K; ++j) {
+    const long long k = K - j;
+    StepArgs<T> st = base_args<T>(c, dt);
+    st.out = bufs[j % 3];
+    st.ldo = S;
+    if (j >= 1) {
+      st.V = bufs[(j - 1) % 3];
+      st.ldv = S;
+    }
+    if (j >= 2) {
+      st.W = bufs[(j - 2) % 3];
+      st.ldw = S;
+    }
+    if (coef[k] != 0.0) {
+      st.X = X;
+      st.ldx = ldx;
+    }
+    st.alpha = (T)coef[k];
+    st.dscale = T(2);
+    st.w1 = (T)(a * c.J1);
+    st.w2 = (T)(a * c.J2);
+    st.gamma = T(-1);
+    launch_step<T>(stream, S, st, shape, num_cu);
+    const int streams = 1 + (st.V ? 1 : 0) + (st.W ? 1 : 0) + (st.X ? 1 : 0);
+    moved += (double)n * (S * bpv * streams + (st.V ? 4.0 + bpv : 0.0));
+  }
+  StepArgs<T> st = base_args<T>(c, dt);
+  st.out = Y;
+  st.ldo = ldy;
+  st.X = X;
+  st.ldx = ldx;
+  st.alpha = (T)(coef[0] / D);
+  if (K >= 1) {
+    st.V = bufs[(K - 1) % 3];
+    st.ldv = S;
+  }
+  if (K >= 2) {
+    st.W = bufs[(K - 2) % 3];
+    st.ldw = S;
+  }
+  st.dscale = (T)(1.0 / D);
+  st.w1 = (T)(a * c.J1 / (2.0 * D));
+  st.w2 = (T)(a * c.J2 / (2.0 * D));
+  st.gamma = (T)(-1.0 / D);
+  launch_step<T>(stream, S, st, shape, num_cu);
+  const int streams = 2 + (st.V ? 1 : 0) + (st.W ? 1 : 0);
+  moved += (double)n * (S * bpv * streams + (st.V ? 4.0 + bpv : 0.0));
+  return moved;
+}
+
+// Graphs pay off where a step is short (launch-bound): blocks up to 64 MB
+// and K up to 2^17 launches per graph.
+template <class T>
+static bool graph_worthwhile(long long n, int S, long long K) {
+  return K >= 16 && K <= (1LL << 17) && (double)n * S * sizeof(T) <= 64.0 * (1 << 20);
+}
+
+template <class T>
+static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, int S,
+                       const T *X, long long ldx, T *Y, long long ldy, long long K,
+                       const std::vector<double> &coef, double D, T *buf3, bool fp32,
+                       double *bytes) {
+  const long long n = c.basis->n;
+  StepShape shape = shape_for(ctx, c.L, S, fp32);
+  if (!ctx->ev_start) {
+    PF_HIP(hipEventCreate(&ctx->ev_start));
+    PF_HIP(hipEventCreate(&ctx->ev_stop));
+  }
+  double moved = 0.0;
+  if (ctx->use_graphs && graph_worthwhile<T>(n, S, K)) {
+    // key: every value baked into the launches
+    std::vector<unsigned long long> key = {
+        (unsigned long long)sizeof(T), (unsigned long long)S, (unsigned long long)n,
+        (unsigned long long)c.L, (unsigned long long)(uintptr_t)X, (unsigned long long)ldx,
+        (unsigned long long)(uintptr_t)Y, (unsigned long long)ldy, (unsigned long long)K,
+        (unsigned long long)(uintptr_t)dt, (unsigned long long)(uintptr_t)buf3,
+        (unsigned long long)(uintptr_t)c.basis->states.p,
+        (unsigned long long)shape.threads, (unsigned long long)shape.lpl,
+        (unsigned long long)shape.wg_per_cu, (unsigned long long)shape.lds_tables};
+    auto bits = [](double v) {
+      unsigned long long u;
+      std::memcpy(&u, &v, sizeof(u));
+      return u;
+    };
+    key.push_back(bits(a));
+    key.push_back(bits(c.J1));
+    key.push_back(bits(c.J2));
+    key.push_back(bits(D));
+    unsigned long long hsh = 1469598103934665603ull;  // FNV-1a over the coefficients
+    for (double v : coef) {
+      hsh ^= bits(v);
+      hsh *= 1099511628211ull;
+    }
+    key.push_back(hsh);
+    if (!(ctx->filter_graph && ctx->filter_graph_key == key)) {
+      if (ctx->filter_graph) {
+        PF_HIP(hipGraphExecDestroy(ctx->filter_graph));
+        ctx->filter_graph = nullptr;
+      }
+      // capture on the context's own stream (the null stream cannot be
+      // captured); the graph is launched on the working stream
+      hipGraph_t g = nullptr;
+      PF_HIP(hipStreamBeginCapture(ctx->own_stream, hipStreamCaptureModeThreadLocal));
+      try {
+        queue_filter<T>(ctx->own_stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
+                        D, buf3);
+      } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(ctx->own_stream, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+      }
+      PF_HIP(hipStreamEndCapture(ctx->own_stream, &g));
+      hipError_t e = hipGraphInstantiate(&ctx->filter_graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      PF_HIP(e);
+      ctx->filter_graph_key = key;
+    }
+    PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
+    PF_HIP(hipGraphLaunch(ctx->filter_graph, ctx->stream));
+    // same byte model as the direct path
+    std::vector<double> none;
+    moved = 0.0;
+    for (long long j = 0; j < K; ++j) {
+      const int streams = 1 + (j >= 1) + (j >= 2) + (coef[K - j] != 0.0);
+      moved += (double)n * (S * (double)sizeof(T) * streams + (j >= 1 ? 4.0 + sizeof(T) : 0.0));
+    }
+    moved += (double)n * (S * (double)sizeof(T) * (2 + (K >= 1) + (K >= 2)) +
+                          (K >= 1 ? 4.0 + sizeof(T) : 0.0));
+  } else {
+    PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
+    moved = queue_filter<T>(ctx->stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
+                            D, buf3);
+  }
+  if (bytes) *bytes += moved;
+  PF_HIP(hipEventRecord(ctx->ev_stop, ctx->stream));
+  PF_HIP(hipEventSynchronize(ctx->ev_stop));
+  float ms = 0.0f;
+  PF_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+  ctx->filter_gpu_s += 1e-3 * ms;
+  ctx->filter_launches += (double)(K + 1);
+  ctx->filter_bytes += moved;
+}
+
+// ------------------------------------------------------- chain helpers --
+
+static void validate_model(const polfed_model *m) {
+  PF_REQUIRE(m != nullptr, "model is NULL");
+  PF_REQUIRE(m->L % 2 == 0, "L must be even");
+  PF_REQUIRE(m->L >= 4 && m->L <= 30, "L must be in [4, 30]");
+  PF_REQUIRE(!(m->J2 != 0.0 && m->L < 6), "J2 != 0 needs L >= 6");
+  PF_REQUIRE(m->h != nullptr, "h is NULL");
+  for (int i = 0; i < m->L; ++i) PF_REQUIRE(std::isfinite(m->h[i]), "h must be finite");
+  PF_REQUIRE(std::isfinite(m->J1) && std::isfinite(m->J2) && std::isfinite(m->Delta),
+             "couplings must be finite");
+}
+
+void make_chain(polfed_ctx *ctx, const polfed_model *m, Chain &c) {
+  validate_model(m);
+  c.L = m->L;
+  c.J1 = m->J1;
+  c.J2 = m->J2;
+  c.Delta = m->Delta;
+  for (int i = 0; i < 32; ++i) c.h[i] = (i < m->L) ? m->h[i] : 0.0;
+  c.basis = &ctx->basis(m->L);
+  c.diag.ensure(sizeof(double) * c.basis->n);
+  launch_diag(ctx->stream, c, c.diag.as<double>());
+}
+
+// ------------------------------------------------------------ bounds --
+
+void run_bounds(polfed_ctx *ctx, const Chain &c, int steps, unsigned long long seed, double &E0,
+                double &E1, double &r0, double &r1) {
+  const long long n = c.basis->n;
+  steps = (int)std::min<long long>(steps, n - 1);
+  if (steps < 1) steps = 1;
+  hipStream_t st = ctx->stream;
+  double *vec = static_cast<double *>(ctx->buf("bnd_vec").ensure(sizeof(double) * 4 * n));
+  double *v[3] = {vec, vec + n, vec + 2 * n};
+  double *w = vec + 3 * n;
+  const int nblk = (int)std::max<long long>(1, std::min<long long>((n + 255) / 256, 4LL * ctx->num_cu));
+  double *sc = static_cast<double *>(
+      ctx->buf("bnd_scal").ensure(sizeof(double) * (2 * (size_t)steps + 2 + 2 * (size_t)nblk)));
+  double *alpha = sc;
+  double *beta = sc + steps;  // beta[0..steps]
+  double *part = sc + 2 * steps + 1;
+  double *part2 = part + nblk;
+  launch_fill(st, beta, 1, 0.0);
+  launch_philox_fill(st, n, 1, v[0], 1, seed, 0x5eedu);
+  launch_dot_partials(st, n, v[0], v[0], part2, nblk);
+  launch_lanczos_normalize(st, n, v[0], v[0], part2, nblk, beta + steps);  // scratch beta slot
+  launch_fill(st, beta, 1, 0.0);
+  for (int k = 0; k < steps; ++k) {
+    double *vk = v[k % 3];
+    double *vprev = (k >= 1) ? v[(k + 2) % 3] : nullptr;
+    double *vnext = v[(k + 1) % 3];
+    StepArgs<double> a = base_args<double>(c, c.diag.as<double>());
+    a.V = vk;
+    a.ldv = 1;
+    a.out = w;
+    a.ldo = 1;
+    a.dscale = 1.0;
+    a.w1 = 0.5 * c.J1;
+    a.w2 = 0.5 * c.J2;
+    launch_step<double>(st, 1, a, shape_for(ctx, c.L, 1, false), ctx->num_cu);
+    launch_dot_partials(st, n, vk, w, part, nblk);
+    launch_lanczos_update(st, n, w, vk, vprev, part, nblk, alpha + k, beta + k, part2);
+    launch_lanczos_normalize(st, n, w, vnext, part2, nblk, beta + k + 1);
+  }
+  std::vector<double> ha(steps), hb(steps + 1);
+  PF_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * steps, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * (steps + 1), hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
+  std::vector<double> off(steps, 0.0);
+  for (int k = 1; k < steps; ++k) off[k] = hb[k];
+  double ylo, yhi;
+  tridiag_extremes(ha, off, E0, E1, ylo, yhi);
+  r0 = std::fabs(hb[steps] * ylo);
+  r1 = std::fabs(hb[steps] * yhi);
+}
+
+// ------------------------------------------------------------- the solve --
+
+struct Lanczos {
+  long long n;
+  int s, P, m_max;
+  double *Q;  // n x P (ld P)
+  double *U, *U2;  // n x s
+  double *T;  // P x P
+};
+
+static int next_pow2_le(int x) {
+  int s = 1;
+  while (s * 2 <= x) s *= 2;
+  return s;
+}
+
+int choose_block(int L, int nev, int precision);
+
+template <class T>
+static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int nev,
+                      double *evals, double *evecs, double *resid, polfed_info *info);
+
+int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opts_in, int nev,
+              double *evals, double *evecs, double *resid, polfed_info *info) {
+  polfed_opts o;
+  polfed_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (o.p <= 0.0) o.p = 0.17;
+  if (o.window_factor <= 0.0) o.window_factor = 1.5;
+  if (o.tol <= 0.0) o.tol = 1e-10;
+  if (o.eta <= 0.0) o.eta = 1e-3;
+  if (o.bounds_steps <= 0) o.bounds_steps = 200;
+  PF_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
+  PF_REQUIRE(evals != nullptr && resid != nullptr, "evals and resid must not be NULL");
+  Chain c;
+  make_chain(ctx, model, c);
+  const long long n = c.basis->n;
+  PF_REQUIRE(nev >= 1 && nev <= n, "nev must be in [1, dim]");
+  PF_REQUIRE(o.target_kind == 0 || o.target_kind == 1, "target_kind must be 0 or 1");
+  if (o.target_kind == 0) PF_REQUIRE(o.target > 0.0 && o.target < 1.0, "eps target must be in (0,1)");
+  if (o.block_size == 0) o.block_size = choose_block(c.L, nev, o.precision);
+  PF_REQUIRE(o.block_size >= 1 && o.block_size <= 64 &&
+                 (o.block_size & (o.block_size - 1)) == 0,
+             "block_size must be a power of two in [1, 64]");
+  if (o.precision == 1)
+    return solve_impl<float>(ctx, c, o, nev, evals, evecs, resid, info);
+  return solve_impl<double>(ctx, c, o, nev, evals, evecs, resid, info);
+}
+
+template <class T>
+static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int nev,
+                      double *evals, double *evecs, double *resid, polfed_info *info) {
+  const bool fp32 = sizeof(T) == 4;
+  hipStream_t st = ctx->stream;
+  const long long n = c.basis->n;
+  polfed_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  const double t_start = now_s();
+  ctx->filter_gpu_s = 0.0;
+  ctx->filter_launches = 0.0;
+  ctx->filter_bytes = 0.0;
+
+  // 1-2: bounds and rescale
+  double E0, E1, r0, r1;
+  run_bounds(ctx, c, o.bounds_steps, o.seed ^ 0xb0b0ull, E0, E1, r0, r1);
+  const double width = E1 - E0;
+  PF_REQUIRE(width > 0.0, "spectrum has zero width");
+  const double E0w = E0 - r0 - o.eta * width, E1w = E1 + r1 + o.eta * width;
+  const double a = 2.0 / (E1w - E0w), b = -(E0w + E1w) / (E1w - E0w);
+  const double sigma_H = (o.target_kind == 0) ? E0 + o.target * width : o.target;
+  const double sigma = a * sigma_H + b;
+  PF_REQUIRE(std::fabs(sigma) < 1.0, "target lies outside the spectral bounds");
+  const double normH = std::max(std::fabs(E0), std::fabs(E1));
+  inf.t_bounds = now_s() - t_start;
+
+  // 3: order
+  const int s = o.block_size;
+  int nwin = (int)std::ceil(o.window_factor * nev);
+  nwin = (int)std::min<long long>(nwin, n);
+  long long K = o.K;
+  double rho = 0.0;
+  if (K <= 0) {
+    const double Gamma = dos_gamma(c.L, c.J1, c.J2, c.Delta, c.h);
+    const double Ebar = trace_mean(c.L, c.J1, c.J2, c.Delta);
+    K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, &rho);
+  }
+  std::vector<double> coef;
+  double D;
+  cheb_coeffs(sigma, K, coef, D);
+
+  // column cap: 4 N_win + 6 s in whole blocks, at most n
+  long long cols = (o.max_cols > 0) ? o.max_cols : 4LL * nwin + 6LL * s;
+  cols = std::min<long long>(cols, (n / s) * s);
+  int m_max = (int)std::max<long long>(1, cols / s);
+  const int P = m_max * s;
+
+  // tau for ||B t~||: FP64 filter 1e-10; FP32 filter its noise floor
+  const double tau = fp32 ? std::max(1e-10, 30.0 * 1.1920929e-7 * std::sqrt((double)K)) : 1e-10;
+
+  // 4: buffers
+  double *Q = static_cast<double *>(ctx->buf("Q").ensure(sizeof(double) * (size_t)n * P));
+  double *U = static_cast<double *>(ctx->buf("U").ensure(sizeof(double) * (size_t)n * s));
+  double *U2 = static_cast<double *>(ctx->buf("U2").ensure(sizeof(double) * (size_t)n * s));
+  double *Tm = static_cast<double *>(ctx->buf("T").ensure(sizeof(double) * (size_t)P * P));
+  double *small = static_cast<double *>(ctx->buf("small").ensure(sizeof(double) * (8 * 64 * 64 + (size_t)P * 64)));
+  double *Ablk = small, *G = small + 4096, *Rinv1 = small + 2 * 4096, *B1 = small + 3 * 4096;
+  double *Rinv2 = small + 4 * 4096, *B2 = small + 5 * 4096, *Bcur = small + 6 * 4096,
+         *BT = small + 7 * 4096, *Cproj = small + 8 * 4096;
+  int *flag = static_cast<int *>(ctx->buf("flag").ensure(64));
+  T *bufs = static_cast<T *>(ctx->buf("cheb").ensure(sizeof(T) * 3 * (size_t)n * s));
+  T *dt = static_cast<T *>(ctx->buf("dt").ensure(sizeof(T) * n));
+  T *Xf = nullptr, *Yf = nullptr;
+  if (fp32) {
+    Xf = static_cast<T *>(ctx->buf("Xf").ensure(sizeof(T) * (size_t)n * s));
+    Yf = static_cast<T *>(ctx->buf("Yf").ensure(sizeof(T) * (size_t)n * s));
+  }
+  DevBuf &partials = ctx->buf("partials");
+  launch_scaled_diag<T>(st, n, c.diag.as<double>(), a, b, dt);
+  launch_fill(st, Tm, (long long)P * P, 0.0);
+
+  // CholeskyQR2 of X (n x s, ld s) into out (ld ldo); B = R factor.
+  // Returns the flag of the first pivot below 1e-14 of the largest diagonal
+  // of the Gram matrix (0 = fine): beyond a condition number of ~1e7
+  // CholeskyQR2 no longer restores orthogonality, and the refill path takes
+  // over.
+  std::vector<int> hf(2);
+  auto cholqr2 = [&](double *X, double *out, long long ldo) -> int {
+    launch_gram(st, n, s, s, X, s, X, s, G, s, partials, ctx->num_cu);
+    launch_chol(st, s, G, Rinv1, B1, flag, 1e-14);
+    launch_update(st, n, s, s, 1.0, X, s, Rinv1, s, 0.0, U2, s);
+    launch_gram(st, n, s, s, U2, s, U2, s, G, s, partials, ctx->num_cu);
+    launch_chol(st, s, G, Rinv2, B2, flag + 1, 1e-14);
+    launch_update(st, n, s, s, 1.0, U2, s, Rinv2, s, 0.0, out, ldo);
+    launch_small_gemm(st, s, s, s, B2, s, B1, s, Bcur, s, 0);
+    PF_HIP(hipMemcpyAsync(hf.data(), flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    PF_HIP(hipStreamSynchronize(st));
+    return hf[0] ? hf[0] : hf[1];
+  };
+
+  double *Usave = static_cast<double *>(ctx->buf("Usave").ensure(sizeof(double) * (size_t)n * s));
+  double *Wg = static_cast<double *>(ctx->buf("Wg").ensure(sizeof(double) * (size_t)s * s * 3 + 2 * s));
+  DevBuf &eigw = ctx->buf("eigwork_small");
+  int refills = 0;
+  auto refill_block = [&](const double *Uorig, double *out, long long ldo, int pc, int j) {
+    ++refills;
+    // eigen-decomposition of G = U^T U
+    launch_gram(st, n, s, s, Uorig, s, Uorig, s, G, s, partials, ctx->num_cu);
+    launch_symmetrize(st, s, G, s);
+    double *lam = Wg + (size_t)2 * s * s, *W = Wg;
+    sym_eig(st, s, G, lam, W, eigw);
+    std::vector<double> hl(s), hW((size_t)s * s);
+    PF_HIP(hipMemcpyAsync(hl.data(), lam, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipMemcpyAsync(hW.data(), W, sizeof(double) * s * s, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipStreamSynchronize(st));
+    const double lmax = std::max(hl[s - 1], 0.0);
+    // kept directions: U w_i / sqrt(lambda_i) for lambda_i > 1e-20 lambda_max
+    std::vector<double> M((size_t)s * s, 0.0);
+    int r = 0;
+    for (int i = s - 1; i >= 0; --i) {
+      if (!(hl[i] > 1e-20 * lmax) || lmax == 0.0) continue;
+      for (int k = 0; k < s; ++k) M[(size_t)k * s + r] = hW[(size_t)k * s + i] / std::sqrt(hl[i]);
+      ++r;
+    }
+    double *Md = Wg + (size_t)s * s;
+    PF_HIP(hipMemcpyAsync(Md, M.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
+    launch_update(st, n, s, s, 1.0, Uorig, s, Md, s, 0.0, U2, s);  // columns >= r are zero
+    if ((long long)pc + s > n) {
+      // no room for s new directions (only at the last block of a tiny
+      // problem, where only B_{j+1} is used): keep the r directions, leave
+      // the rest zero
+      launch_cast<double, double>(st, n, s, U2, s, out, ldo);
+      launch_gram(st, n, s, s, out, ldo, Uorig, s, Bcur, s, partials, ctx->num_cu);
+      return;
+    }
+    // random columns r..s-1, then the whole block against Qm (twice) and QR
+    launch_philox_fill(st, n, s - r, U2 + r, s, o.seed + 977ull * (j + 1) + 13ull * refills, 2u);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_gram(st, n, pc, s, Q, P, U2, s, Cproj, s, partials, ctx->num_cu);
+      launch_update(st, n, pc, s, -1.0, Q, P, Cproj, s, 1.0, U2, s);
+    }
+    PF_HIP(hipMemcpyAsync(U, U2, sizeof(double) * n * s, hipMemcpyDeviceToDevice, st));
+    if (cholqr2(U, out, ldo) != 0)
+      throw Error(POLFED_EBREAKDOWN, "Lanczos block lost rank and could not be refilled");
+    // B_{j+1} = Q_{j+1}^T U_orig
+    launch_gram(st, n, s, s, out, ldo, Uorig, s, Bcur, s, partials, ctx->num_cu);
+  };
+
+  // start block
+  launch_philox_fill(st, n, s, U, s, o.seed, 1u);
+  if (cholqr2(U, Q, P) != 0) throw Error(POLFED_EBREAKDOWN, "start block is rank deficient");
+
+  double t_filter = 0, t_orth = 0, t_eig = 0;
+  double bytes = 0.0;
+  int m_done = 0, nconv = 0;
+  std::vector<double> theta, tres;
+  double *Tw = static_cast<double *>(ctx->buf("Tw").ensure(sizeof(double) * (size_t)P * P));
+  double *Vt = static_cast<double *>(ctx->buf("Vt").ensure(sizeof(double) * (size_t)P * P));
+  double *th = static_cast<double *>(ctx->buf("theta").ensure(sizeof(double) * (size_t)P * 2));
+  double *Rres = static_cast<double *>(ctx->buf("Rres").ensure(sizeof(double) * (size_t)64 * P));
+  DevBuf &eigwork = ctx->buf("eigwork");
+  const int check_from = std::max(s, std::min(nev, P));  // columns before the first T_m check
+
+  for (int j = 0; j < m_max; ++j) {
+    double t0 = now_s();
+    double *Qj = Q + (size_t)j * s;
+    // U = P(H~) Q_j
+    if (fp32) {
+      launch_cast<double, float>(st, n, s, Qj, P, reinterpret_cast<float *>(Xf), s);
+      run_filter<T>(ctx, c, dt, a, s, Xf, s, Yf, s, K, coef, D, bufs, true, &bytes);
+      launch_cast<float, double>(st, n, s, reinterpret_cast<float *>(Yf), s, U, s);
+    } else {
+      // stage Q_j in a fixed buffer so that the filter's graph is the same
+      // for every block
+      double *Xs = static_cast<double *>(ctx->buf("Xs").ensure(sizeof(double) * (size_t)n * s));
+      launch_cast<double, double>(st, n, s, Qj, P, Xs, s);
+      run_filter<T>(ctx, c, dt, a, s, reinterpret_cast<T *>(Xs), s, reinterpret_cast<T *>(U), s,
+                    K, coef, D, bufs, false, &bytes);
+    }
+    PF_HIP(hipStreamSynchronize(st));
+    double t1 = now_s();
+    t_filter += t1 - t0;
+    // Lan1: U -= Q_{j-1} B_j^T ; A_j = sym(Q_j^T U) ; U -= Q_j A_j
+    if (j > 0) launch_update(st, n, s, s, -1.0, Q + (size_t)(j - 1) * s, P, BT, s, 1.0, U, s);
+    launch_gram(st, n, s, s, Qj, P, U, s, Ablk, s, partials, ctx->num_cu);
+    launch_symmetrize(st, s, Ablk, s);
+    launch_update(st, n, s, s, -1.0, Qj, P, Ablk, s, 1.0, U, s);
+    PF_HIP(hipMemcpy2DAsync(Tm + (size_t)j * s * P + j * s, sizeof(double) * P, Ablk,
+                            sizeof(double) * s, sizeof(double) * s, s, hipMemcpyDeviceToDevice,
+                            st));
+    // full reorthogonalisation against Q_1..Q_j, twice
+    const int pc = (j + 1) * s;
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_gram(st, n, pc, s, Q, P, U, s, Cproj, s, partials, ctx->num_cu);
+      launch_update(st, n, pc, s, -1.0, Q, P, Cproj, s, 1.0, U, s);
+    }
+    // Lan2: Q_{j+1} B_{j+1} = U
+    // (no slot left after the last block: Q_{j+1} lands in U, only B_{j+1}
+    // is needed)
+    double *Qnext = (j + 1 < m_max) ? Q + (size_t)(j + 1) * s : U;
+    long long ldq = (j + 1 < m_max) ? P : s;
+    PF_HIP(hipMemcpyAsync(Usave, U, sizeof(double) * n * s, hipMemcpyDeviceToDevice, st));
+    int bad = cholqr2(U, Qnext, ldq);
+    if (bad != 0) {
+      // The block lost rank (the Krylov space is nearly exhausted, which
+      // happens when n is small).  Keep the well-conditioned directions of U
+      // and refill the rest with random vectors orthogonal to Qm; then
+      // B_{j+1} = Q_{j+1}^T U, so that U = Q_{j+1} B_{j+1} still holds on the
+      // kept directions (B is no longer triangular; T_m does not need it).
+      refill_block(Usave, Qnext, ldq, pc, j);
+    }
+    launch_small_transpose(st, s, s, Bcur, s, BT, s);
+    if (j + 1 < m_max) {
+      PF_HIP(hipMemcpy2DAsync(Tm + (size_t)(j + 1) * s * P + j * s, sizeof(double) * P, Bcur,
+                              sizeof(double) * s, sizeof(double) * s, s,
+                              hipMemcpyDeviceToDevice, st));
+      PF_HIP(hipMemcpy2DAsync(Tm + (size_t)j * s * P + (j + 1) * s, sizeof(double) * P, BT,
+                              sizeof(double) * s, sizeof(double) * s, s,
+                              hipMemcpyDeviceToDevice, st));
+    }
+    double t2 = now_s();
+    t_orth += t2 - t1;
+    m_done = j + 1;
+    const int ms = m_done * s;
+    // eigenpairs of T_m and the convergence test
+    if (ms >= check_from || j + 1 == m_max) {
+      PF_HIP(hipMemcpy2DAsync(Tw, sizeof(double) * ms, Tm, sizeof(double) * P,
+                              sizeof(double) * ms, ms, hipMemcpyDeviceToDevice, st));
+      sym_eig(st, ms, Tw, th, Vt, eigwork);
+      // R = B_{j+1} * V[ms-s:ms, :]  (s x ms), residual_i = ||R[:, i]||
+      launch_small_gemm(st, s, s, ms, Bcur, s, Vt + (size_t)(ms - s) * ms, ms, Rres, ms, 0);
+      launch_colnorms(st, s, ms, Rres, ms, th + ms, partials, ctx->num_cu);
+      theta.resize(ms);
+      tres.resize(ms);
+      PF_HIP(hipMemcpyAsync(theta.data(), th, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
+      PF_HIP(hipMemcpyAsync(tres.data(), th + ms, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
+      PF_HIP(hipStreamSynchronize(st));
+      nconv = 0;
+      for (int i = 0; i < ms; ++i)
+        if (theta[i] >= o.p && tres[i] <= tau) ++nconv;
+      t_eig += now_s() - t2;
+      if (nconv >= nev) break;
+    }
+  }
+  const int ms = m_done * s;
+  const bool converged = nconv >= nev;
+
+  // 7: Ritz vectors of the candidates (theta >= p, else the nev largest)
+  double t3 = now_s();
+  std::vector<int> cand;
+  for (int i = 0; i < ms; ++i)
+    if (theta[i] >= o.p) cand.push_back(i);
+  if ((int)cand.size() < nev) {
+    cand.clear();
+    for (int i = ms - 1; i >= 0 && (int)cand.size() < nev; --i) cand.push_back(i);
+    std::sort(cand.begin(), cand.end());
+  }
+  const int nc = (int)cand.size();
+  const int ldr = ((nc + 7) / 8) * 8;
+  int *didx = static_cast<int *>(ctx->buf("idx").ensure(sizeof(int) * std::max(nc, nev) * 2));
+  PF_HIP(hipMemcpyAsync(didx, cand.data(), sizeof(int) * nc, hipMemcpyHostToDevice, st));
+  double *Tsel = static_cast<double *>(ctx->buf("Tsel").ensure(sizeof(double) * (size_t)ms * ldr));
+  launch_gather_cols(st, ms, nc, Vt, ms, didx, Tsel, ldr);
+  double *UR = static_cast<double *>(ctx->buf("UR").ensure(sizeof(double) * (size_t)n * ldr));
+  double *WR = static_cast<double *>(ctx->buf("WR").ensure(sizeof(double) * (size_t)n * ldr));
+  double *Urot = static_cast<double *>(ctx->buf("Urot").ensure(sizeof(double) * (size_t)n * ldr));
+  for (int c0 = 0; c0 < nc; c0 += 64) {
+    const int w = std::min(64, nc - c0);
+    launch_update(st, n, ms, w, 1.0, Q, P, Tsel + c0, ldr, 0.0, UR + c0, ldr);
+  }
+  double *dt64 = static_cast<double *>(ctx->buf("dt64").ensure(sizeof(double) * n));
+  launch_scaled_diag<double>(st, n, c.diag.as<double>(), a, b, dt64);
+  double *Gr = static_cast<double *>(ctx->buf("Gr").ensure(sizeof(double) * (size_t)nc * nc * 2 + 16));
+  double *Yr = Gr + (size_t)nc * nc;
+  double *epsd = static_cast<double *>(ctx->buf("epsd").ensure(sizeof(double) * (size_t)nc));
+  const int nout = std::min(nev, nc);
+  const int ldo = ((nout + 7) / 8) * 8;
+  double *Vout = static_cast<double *>(ctx->buf("Vout").ensure(sizeof(double) * (size_t)n * ldo));
+  double *HV = static_cast<double *>(ctx->buf("HV").ensure(sizeof(double) * (size_t)n * ldo));
+  double *vecs = static_cast<double *>(ctx->buf("vecs").ensure(sizeof(double) * 4 * (size_t)ldo));
+  double *nrm = vecs, *Ed = vecs + ldo, *rd = vecs + 2 * ldo, *sg = vecs + 3 * ldo;
+  double *Msc = static_cast<double *>(ctx->buf("Msc").ensure(sizeof(double) * (size_t)nc * nc));
+  std::vector<double> Esel(nout), r(nout);
+  double refine_bytes = 0.0, t_refine = 0.0, rr_apps = 0.0;
+  std::vector<double> coef_rv;
+  double D_r = 1.0;
+  auto coef_r = [&](long long Kr, double sg_) -> const std::vector<double> & {
+    cheb_coeffs(sg_, Kr, coef_rv, D_r);
+    return coef_rv;
+  };
+  int passes = 0;
+  long long K_r = std::max<long long>(8, K / 4);
+  const bool verbose = std::getenv("POLFED_VERBOSE") != nullptr;
+  int nref = nc;  // columns carried through Rayleigh-Ritz (shrinks once refining)
+
+  // SVQB: X (n x q, ld) <- X W Lambda^{-1/2} from the eigenpairs of X^T X
+  auto svqb = [&](double *X, long long ldx, int q) {
+    launch_gram(st, n, q, q, X, ldx, X, ldx, Gr, q, partials, ctx->num_cu);
+    launch_symmetrize(st, q, Gr, q);
+    sym_eig(st, q, Gr, epsd, Yr, eigwork);
+    std::vector<double> lam(q), W((size_t)q * q);
+    PF_HIP(hipMemcpyAsync(lam.data(), epsd, sizeof(double) * q, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipMemcpyAsync(W.data(), Yr, sizeof(double) * q * q, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipStreamSynchronize(st));
+    const double lmax = lam[q - 1];
+    for (int i = 0; i < q; ++i) {
+      const double f = (lam[i] > 1e-28 * lmax) ? 1.0 / std::sqrt(lam[i]) : 0.0;
+      for (int k = 0; k < q; ++k) W[(size_t)k * q + i] *= f;
+    }
+    PF_HIP(hipMemcpyAsync(Msc, W.data(), sizeof(double) * q * q, hipMemcpyHostToDevice, st));
+    for (int c0 = 0; c0 < q; c0 += 64) {
+      const int w = std::min(64, q - c0);
+      launch_update(st, n, q, w, 1.0, X, ldx, Msc + c0, q, 0.0, Urot + c0, ldr);
+    }
+    PF_HIP(hipMemcpy2DAsync(X, sizeof(double) * ldx, Urot, sizeof(double) * ldr,
+                            sizeof(double) * q, n, hipMemcpyDeviceToDevice, st));
+  };
+
+  for (;;) {
+    // Rayleigh-Ritz of H~ on span(UR): Urot = UR Y, E = (eps - b)/a
+    apply_op<double>(ctx, c, dt64, 0.5 * a * c.J1, 0.5 * a * c.J2, UR, ldr, WR, ldr, nref, false);
+    rr_apps += nref;
+    launch_gram(st, n, nref, nref, UR, ldr, WR, ldr, Gr, nref, partials, ctx->num_cu);
+    launch_symmetrize(st, nref, Gr, nref);
+    sym_eig(st, nref, Gr, epsd, Yr, eigwork);
+    for (int c0 = 0; c0 < nref; c0 += 64) {
+      const int w = std::min(64, nref - c0);
+      launch_update(st, n, nref, w, 1.0, UR, ldr, Yr + c0, nref, 0.0, Urot + c0, ldr);
+    }
+    std::vector<double> eps(nref);
+    PF_HIP(hipMemcpyAsync(eps.data(), epsd, sizeof(double) * nref, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipStreamSynchronize(st));
+    std::vector<double> E(nref);
+    for (int i = 0; i < nref; ++i) E[i] = (eps[i] - b) / a;
+    // the nev nearest sigma_H (ties -> lower E), ascending
+    std::vector<int> ord(nref);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+      const double dx = std::fabs(E[x] - sigma_H), dy = std::fabs(E[y] - sigma_H);
+      if (dx != dy) return dx < dy;
+      return E[x] < E[y];
+    });
+    std::vector<int> sel(ord.begin(), ord.begin() + nout);
+    std::sort(sel.begin(), sel.end(), [&](int x, int y) { return E[x] < E[y]; });
+    for (int i = 0; i < nout; ++i) Esel[i] = E[sel[i]];
+    PF_HIP(hipMemcpyAsync(didx, sel.data(), sizeof(int) * nout, hipMemcpyHostToDevice, st));
+    launch_gather_cols(st, n, nout, Urot, ldr, didx, Vout, ldo);
+    // normalise, sign fix, residuals ||Hv - Ev|| with the unscaled H
+    launch_colnorms(st, n, nout, Vout, ldo, nrm, partials, ctx->num_cu);
+    std::vector<double> hn(nout);
+    PF_HIP(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < nout; ++i) hn[i] = 1.0 / hn[i];
+    PF_HIP(hipMemcpyAsync(nrm, hn.data(), sizeof(double) * nout, hipMemcpyHostToDevice, st));
+    launch_scale_cols(st, n, nout, Vout, ldo, nrm);
+    launch_sign_factors(st, n, nout, Vout, ldo, sg, partials, ctx->num_cu);
+    launch_scale_cols(st, n, nout, Vout, ldo, sg);
+    apply_op<double>(ctx, c, c.diag.as<double>(), 0.5 * c.J1, 0.5 * c.J2, Vout, ldo, HV, ldo,
+                     nout, false);
+    rr_apps += nout;
+    PF_HIP(hipMemcpyAsync(Ed, Esel.data(), sizeof(double) * nout, hipMemcpyHostToDevice, st));
+    launch_resid_norms(st, n, nout, HV, ldo, Vout, ldo, Ed, rd, partials, ctx->num_cu);
+    PF_HIP(hipMemcpyAsync(r.data(), rd, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipStreamSynchronize(st));
+    double rmax = 0.0;
+    for (int i = 0; i < nout; ++i) rmax = std::max(rmax, r[i]);
+    if (verbose)
+      fprintf(stderr, "[polfed] rr pass %d: K_r %lld, %d vectors, max resid / ||H|| = %.3e\n",
+              passes, passes ? K_r : 0LL, nref, rmax / normH);
+    if (!fp32 || rmax <= o.tol * normH || passes >= 4) break;
+
+    // FP64 refinement (FP32-filter mode): the FP32 rounding of the filter
+    // leaves broadband error components ~eps32 sqrt(K) in the Ritz vectors;
+    // an FP64 filter of order K_r damps a component at distance u (in the
+    // angle of x = cos u) from the target by ~1/(K_r u) while keeping the
+    // wanted ones near 1, and Rayleigh-Ritz on the filtered span removes the
+    // mixing.  Subspace iteration on the nout + margin vectors nearest the
+    // target; K_r = K/4, K/2, K, K on successive passes.
+    const double tr0 = now_s();
+    double *cheb64 = static_cast<double *>(ctx->buf("cheb64").ensure(sizeof(double) * 3 * (size_t)n * 64));
+    // refine the nout + margin Ritz vectors nearest the target: gather them
+    // (ordered by distance) to the front of Urot
+    const int q = std::min(nref, nout + std::max(8, nout / 4));
+    {
+      std::vector<int> near(ord.begin(), ord.begin() + q);
+      PF_HIP(hipMemcpyAsync(didx, near.data(), sizeof(int) * q, hipMemcpyHostToDevice, st));
+      launch_gather_cols(st, n, q, Urot, ldr, didx, WR, ldr);
+    }
+    const std::vector<double> &cr = coef_r(K_r, sigma);
+    for (int c0 = 0; c0 < q;) {
+      int w = 64;
+      while (w > q - c0) w >>= 1;
+      run_filter<double>(ctx, c, dt64, a, w, WR + c0, ldr, UR + c0, ldr, K_r, cr, D_r, cheb64,
+                         false, &refine_bytes);
+      c0 += w;
+    }
+    nref = q;
+    svqb(UR, ldr, nref);
+    svqb(UR, ldr, nref);
+    PF_HIP(hipStreamSynchronize(st));
+    t_refine += now_s() - tr0;
+    rr_apps += (double)(K_r + 1) * nref;
+    ++passes;
+    K_r = std::min<long long>(2 * K_r, K);
+  }
+  if (evecs) {
+    double *cm = static_cast<double *>(ctx->buf("colmajor").ensure(sizeof(double) * (size_t)n * nout));
+    launch_to_colmajor(st, n, nout, Vout, ldo, cm);
+    PF_HIP(hipMemcpyAsync(evecs, cm, sizeof(double) * (size_t)n * nout, hipMemcpyDeviceToHost, st));
+  }
+  PF_HIP(hipStreamSynchronize(st));
+  double t_rr = now_s() - t3 - t_refine;
+
+  for (int i = 0; i < nout; ++i) {
+    evals[i] = Esel[i];
+    resid[i] = r[i];
+  }
+  for (int i = nout; i < nev; ++i) {
+    evals[i] = NAN;
+    resid[i] = NAN;
+  }
+  int n_ok = 0;
+  double rmax = 0.0;
+  for (int i = 0; i < nout; ++i) {
+    if (r[i] <= o.tol * normH) ++n_ok;
+    rmax = std::max(rmax, r[i]);
+  }
+  inf.E0 = E0;
+  inf.E1 = E1;
+  inf.E0w = E0w;
+  inf.E1w = E1w;
+  inf.sigma_energy = sigma_H;
+  inf.sigma_tilde = sigma;
+  inf.normH = normH;
+  inf.K = K;
+  inf.nev_window = nwin;
+  inf.block_size = s;
+  inf.m = m_done;
+  inf.n_conv = n_ok;
+  inf.refine_passes = passes;
+  inf.t_refine = t_refine;
+  inf.max_resid = rmax;
+  inf.t_filter = t_filter;
+  inf.t_orth = t_orth;
+  inf.t_eig = t_eig;
+  inf.t_rr = t_rr;
+  inf.t_total = now_s() - t_start;
+  inf.hv_apps = (double)(K + 1) * ms + rr_apps + o.bounds_steps;
+  inf.filter_bytes = bytes + refine_bytes;
+  inf.filter_gpu_s = ctx->filter_gpu_s;
+  inf.filter_launches = ctx->filter_launches;
+  if (info) *info = inf;
+  return (converged && nout == nev) ? POLFED_OK : POLFED_NOT_CONVERGED;
+}
+
+// ------------------------------------------------- stage-call helpers --
+
+template <class T>
+void stage_apply_h(polfed_ctx *ctx, const Chain &c, int nvec, const T *X, T *Y) {
+  const long long n = c.basis->n;
+  T *dt = static_cast<T *>(ctx->buf("stage_dt").ensure(sizeof(T) * n));
+  launch_scaled_diag<T>(ctx->stream, n, c.diag.as<double>(), 1.0, 0.0, dt);
+  apply_op<T>(ctx, c, dt, 0.5 * c.J1, 0.5 * c.J2, X, nvec, Y, nvec, nvec, sizeof(T) == 4);
+}
+
+template <class T>
+void stage_apply_filter(polfed_ctx *ctx, const Chain &c, double E0, double E1, double sigma,
+                        long long K, int nvec, const T *X, T *Y) {
+  const long long n = c.basis->n;
+  const double a = 2.0 / (E1 - E0), b = -(E0 + E1) / (E1 - E0);
+  T *dt = static_cast<T *>(ctx->buf("stage_dt").ensure(sizeof(T) * n));
+  launch_scaled_diag<T>(ctx->stream, n, c.diag.as<double>(), a, b, dt);
+  T *bufs = static_cast<T *>(ctx->buf("stage_cheb").ensure(sizeof(T) * 3 * (size_t)n * nvec));
+  std::vector<double> coef;
+  double D;
+  cheb_coeffs(sigma, K, coef, D);
+  run_filter<T>(ctx, c, dt, a, nvec, X, nvec, Y, nvec, K, coef, D, bufs, sizeof(T) == 4, nullptr);
+}
+
+template void stage_apply_h<float>(polfed_ctx *, const Chain &, int, const float *, float *);
+template void stage_apply_h<double>(polfed_ctx *, const Chain &, int, const double *, double *);
+template void stage_apply_filter<float>(polfed_ctx *, const Chain &, double, double, double,
+                                        long long, int, const float *, float *);
+template void stage_apply_filter<double>(polfed_ctx *, const Chain &, double, double, double,
+                                         long long, int, const double *, double *);
+
+// ----------------------------------------------------------- tuning --
+
+StepShape default_shape(int L, int S, bool fp32) {
+  // From a sweep of (threads, loads per lane, groups per CU, LDS tables) on
+  // gfx950: two 16-byte loads per lane win for every L; large chains
+  // (L >= 22, 16-64 KB of rank tables per group) prefer two 1024-thread
+  // groups per CU, mid-size ones sixteen 256-thread groups.
+  StepShape sh;
+  sh.lds_tables = 1;
+  sh.lpl = 2;
+  if (L <= 16) {
+    sh.threads = 256;
+    sh.wg_per_cu = 8;
+    sh.lpl = 1;
+  } else if (L == 18) {
+    sh.threads = 1024;
+    sh.wg_per_cu = 2;
+  } else if (L <= 20) {
+    sh.threads = 256;
+    sh.wg_per_cu = 16;
+  } else {
+    sh.threads = 1024;
+    sh.wg_per_cu = 2;
+    if (L == 24 || (L == 22 && fp32)) sh.lpl = 1;
+  }
+  (void)S;
+  return sh;
+}
+
+int choose_block(int L, int nev, int precision) {
+  int s = next_pow2_le(std::max(1, nev / 4));
+  s = std::min(s, precision ? 32 : 16);
+  if (L <= 14) s = std::min(s, 8);
+  return std::max(1, s);
+}
+
+}  // namespace polfed

@@ -1,0 +1,87 @@
+"""The C-ABI library: loads, exports every declared entry point, and its host
+math (no device work) agrees with the oracle.  No GPU needed."""
+
+import ctypes
+from math import comb
+
+import numpy as np
+import pytest
+
+from oracle import chebyshev
+from paper_2005_09534_amd import polfed as pf
+from paper_2005_09534_amd import workloads
+
+
+def test_library_exports_every_declared_symbol():
+    names = pf.header_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(pf.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("L", [2, 4, 12, 18, 22, 26, 30])
+def test_dim(L):
+    assert pf.dim(L) == comb(L, L // 2)
+
+
+@pytest.mark.parametrize("L", [1, 3, 0, 32, -2])
+def test_dim_invalid(L):
+    assert pf.dim(L) == -1
+
+
+def test_default_opts():
+    o = pf.default_opts()
+    assert o.target == 0.5 and o.p == 0.17 and o.window_factor == 1.5 and o.tol == 1e-10
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.37, -0.8])
+@pytest.mark.parametrize("K", [0, 1, 7, 200, 5001])
+def test_cheb_coeffs_match_oracle(sigma, K):
+    c, D = pf.cheb_coeffs(sigma, K)
+    # cos(n arccos sigma): a rounding of arccos is amplified n times in the
+    # phase (argument n arccos(sigma) carries ~n eps absolute error), so
+    # coefficients agree to ~2 n eps (the library evaluates sigma = 0
+    # exactly)
+    n = np.arange(K + 1)
+    assert (np.abs(c - chebyshev.cheb_coeffs(sigma, K)) <= 2e-15 * (n + 4)).all()
+    assert abs(D - chebyshev.norm_D(sigma, K)) < 1e-10 * max(1.0, D)
+
+
+def test_cheb_coeffs_invalid():
+    c = np.empty(3)
+    d = ctypes.c_double()
+    assert pf.LIB.polfed_cheb_coeffs(1.0, 2, c.ctypes.data_as(pf.P_double), ctypes.byref(d)) == pf.EINVAL
+    assert pf.LIB.polfed_cheb_coeffs(0.0, -1, c.ctypes.data_as(pf.P_double), ctypes.byref(d)) == pf.EINVAL
+
+
+@pytest.mark.parametrize("L,W,J2,nwin,sigma", [(12, 3.0, 0.0, 30, 0.0), (16, 1.0, 0.0, 75, 0.1),
+                                                 (18, 2.0, 1.0, 75, 0.0), (22, 5.0, 0.0, 150, -0.05),
+                                                 (26, 4.0, 0.0, 150, 0.0)])
+def test_filter_order_matches_oracle(L, W, J2, nwin, sigma):
+    """K from the density of states: integer-exact against the oracle's rule
+    (same FP64 decisions, independent evaluation of P: closed form vs sum)."""
+    c = workloads.chain(L, W, 7, J2=J2)
+    m = pf.make_model(L, c.J1, c.J2, c.Delta, c.h)
+    E0w, E1w = -0.9 * L, 0.85 * L
+    K, rho = pf.filter_order(m, E0w, E1w, sigma, nwin)
+    N = comb(L, L // 2)
+    Ebar = -(c.J1 + c.J2) * c.Delta * L / (4.0 * (L - 1))
+    G = chebyshev.dos_gamma(L, c.J1, c.J2, c.Delta, c.h)
+    if K <= 3000:
+        Ko = chebyshev.choose_K(nwin, sigma, 0.17, N, Ebar, G, E0w, E1w)
+        assert K == Ko
+    # the rule's defining inequalities, evaluated by the oracle
+    f = lambda k: chebyshev.n_P(k, sigma, 0.17, N, Ebar, G, E0w, E1w)
+    if K <= 20000:
+        assert f(K) >= nwin > f(K + 1)
+    assert abs(rho - chebyshev.rho_tilde(sigma, N, Ebar, G, E0w, E1w)) < 1e-9 * rho
+
+
+def test_create_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = ctypes.c_void_p()
+    rc = pf.LIB.polfed_create(0, ctypes.byref(h))
+    assert rc < 0 and not h.value

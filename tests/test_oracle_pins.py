@@ -291,7 +291,8 @@ def test_solve_c1_vs_dense():
     assert res["resid"].max() <= 1e-8 * normH
     # eigenvectors: |<u, v>| = 1 up to the Davis-Kahan bound
     ov = np.abs(np.sum(res["V"] * Vd, axis=0))
-    gaps = np.array([np.min(np.abs(np.delete(dense.full_spectrum(H), np.argmin(np.abs(dense.full_spectrum(H) - e))) - e)) for e in Ed])
+    w = dense.full_spectrum(H)
+    gaps = np.array([np.min(np.abs(np.delete(w, np.argmin(np.abs(w - e))) - e)) for e in Ed])
     assert (1 - ov <= (res["resid"] / gaps) ** 2 + 1e-10).all()
 
 
@@ -363,3 +364,17 @@ def test_seed_and_block_invariance():
     r1 = lanczos.solve(L, 1.0, 0.0, 1.0, h, nev, 2, rng_seed=1)
     r2 = lanczos.solve(L, 1.0, 0.0, 1.0, h, nev, 4, rng_seed=2)
     assert np.abs(r1["E"] - r2["E"]).max() < 1e-10 * max(abs(r1["E0"]), abs(r1["E1"]))
+
+
+def test_hamiltonian_row_matches_csr():
+    """The per-row form used for sampled checks at large L equals the CSR."""
+    L = 10
+    h = np.random.default_rng(2).uniform(-1, 1, L)
+    H = chain.hamiltonian_csr(L, 1.0, 0.6, 0.9, h).tocsr()
+    b = chain.basis(L)
+    for r in (0, 7, 100, len(b) - 1):
+        row = chain.hamiltonian_row(L, 1.0, 0.6, 0.9, h, b[r])
+        dense_row = np.zeros(len(b))
+        for st, v in row.items():
+            dense_row[chain.rank([st], b)[0]] += v
+        assert np.abs(dense_row - H.getrow(r).toarray().ravel()).max() < 1e-14
