@@ -24,6 +24,7 @@
 // everything else in FP64; a refinement in FP64 follows (see refine()).
 #include <algorithm>
 #include <chrono>
+#include <iterator>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -609,107 +610,32 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
   const int ms = m_done * s;
   const bool converged = nconv >= nev;
 
-  // 7: Ritz vectors of the candidates (theta >= p, else the nev largest)
+  // 7: Rayleigh-Ritz of H~, selection of the nev nearest the target, and
+  // residuals with the unscaled H
   double t3 = now_s();
-  std::vector<int> cand;
-  for (int i = 0; i < ms; ++i)
-    if (theta[i] >= o.p) cand.push_back(i);
-  if ((int)cand.size() < nev) {
-    cand.clear();
-    for (int i = ms - 1; i >= 0 && (int)cand.size() < nev; --i) cand.push_back(i);
-    std::sort(cand.begin(), cand.end());
-  }
-  const int nc = (int)cand.size();
-  const int ldr = ((nc + 7) / 8) * 8;
-  int *didx = static_cast<int *>(ctx->buf("idx").ensure(sizeof(int) * std::max(nc, nev) * 2));
-  PF_HIP(hipMemcpyAsync(didx, cand.data(), sizeof(int) * nc, hipMemcpyHostToDevice, st));
-  double *Tsel = static_cast<double *>(ctx->buf("Tsel").ensure(sizeof(double) * (size_t)ms * ldr));
-  launch_gather_cols(st, ms, nc, Vt, ms, didx, Tsel, ldr);
-  double *UR = static_cast<double *>(ctx->buf("UR").ensure(sizeof(double) * (size_t)n * ldr));
-  double *WR = static_cast<double *>(ctx->buf("WR").ensure(sizeof(double) * (size_t)n * ldr));
-  double *Urot = static_cast<double *>(ctx->buf("Urot").ensure(sizeof(double) * (size_t)n * ldr));
-  for (int c0 = 0; c0 < nc; c0 += 64) {
-    const int w = std::min(64, nc - c0);
-    launch_update(st, n, ms, w, 1.0, Q, P, Tsel + c0, ldr, 0.0, UR + c0, ldr);
-  }
   double *dt64 = static_cast<double *>(ctx->buf("dt64").ensure(sizeof(double) * n));
   launch_scaled_diag<double>(st, n, c.diag.as<double>(), a, b, dt64);
-  double *Gr = static_cast<double *>(ctx->buf("Gr").ensure(sizeof(double) * (size_t)nc * nc * 2 + 16));
-  double *Yr = Gr + (size_t)nc * nc;
-  double *epsd = static_cast<double *>(ctx->buf("epsd").ensure(sizeof(double) * (size_t)nc));
-  const int nout = std::min(nev, nc);
-  const int ldo = ((nout + 7) / 8) * 8;
+  const int nout_max = std::min<long long>(nev, ms);
+  const int ldo = ((nout_max + 7) / 8) * 8;
   double *Vout = static_cast<double *>(ctx->buf("Vout").ensure(sizeof(double) * (size_t)n * ldo));
   double *HV = static_cast<double *>(ctx->buf("HV").ensure(sizeof(double) * (size_t)n * ldo));
   double *vecs = static_cast<double *>(ctx->buf("vecs").ensure(sizeof(double) * 4 * (size_t)ldo));
   double *nrm = vecs, *Ed = vecs + ldo, *rd = vecs + 2 * ldo, *sg = vecs + 3 * ldo;
-  double *Msc = static_cast<double *>(ctx->buf("Msc").ensure(sizeof(double) * (size_t)nc * nc));
-  std::vector<double> Esel(nout), r(nout);
+  int *didx = static_cast<int *>(ctx->buf("idx").ensure(sizeof(int) * (size_t)(P + 64) * 2));
+  std::vector<double> Esel, r;
   double refine_bytes = 0.0, t_refine = 0.0, rr_apps = 0.0;
-  std::vector<double> coef_rv;
-  double D_r = 1.0;
-  auto coef_r = [&](long long Kr, double sg_) -> const std::vector<double> & {
-    cheb_coeffs(sg_, Kr, coef_rv, D_r);
-    return coef_rv;
-  };
-  int passes = 0;
-  long long K_r = std::max<long long>(8, K / 4);
+  int passes = 0, nout = 0;
   const bool verbose = std::getenv("POLFED_VERBOSE") != nullptr;
-  int nref = nc;  // columns carried through Rayleigh-Ritz (shrinks once refining)
 
-  // SVQB: X (n x q, ld) <- X W Lambda^{-1/2} from the eigenpairs of X^T X
-  auto svqb = [&](double *X, long long ldx, int q) {
-    launch_gram(st, n, q, q, X, ldx, X, ldx, Gr, q, partials, ctx->num_cu);
-    launch_symmetrize(st, q, Gr, q);
-    sym_eig(st, q, Gr, epsd, Yr, eigwork);
-    std::vector<double> lam(q), W((size_t)q * q);
-    PF_HIP(hipMemcpyAsync(lam.data(), epsd, sizeof(double) * q, hipMemcpyDeviceToHost, st));
-    PF_HIP(hipMemcpyAsync(W.data(), Yr, sizeof(double) * q * q, hipMemcpyDeviceToHost, st));
-    PF_HIP(hipStreamSynchronize(st));
-    const double lmax = lam[q - 1];
-    for (int i = 0; i < q; ++i) {
-      const double f = (lam[i] > 1e-28 * lmax) ? 1.0 / std::sqrt(lam[i]) : 0.0;
-      for (int k = 0; k < q; ++k) W[(size_t)k * q + i] *= f;
-    }
-    PF_HIP(hipMemcpyAsync(Msc, W.data(), sizeof(double) * q * q, hipMemcpyHostToDevice, st));
-    for (int c0 = 0; c0 < q; c0 += 64) {
-      const int w = std::min(64, q - c0);
-      launch_update(st, n, q, w, 1.0, X, ldx, Msc + c0, q, 0.0, Urot + c0, ldr);
-    }
-    PF_HIP(hipMemcpy2DAsync(X, sizeof(double) * ldx, Urot, sizeof(double) * ldr,
-                            sizeof(double) * q, n, hipMemcpyDeviceToDevice, st));
-  };
-
-  for (;;) {
-    // Rayleigh-Ritz of H~ on span(UR): Urot = UR Y, E = (eps - b)/a
-    apply_op<double>(ctx, c, dt64, 0.5 * a * c.J1, 0.5 * a * c.J2, UR, ldr, WR, ldr, nref, false);
-    rr_apps += nref;
-    launch_gram(st, n, nref, nref, UR, ldr, WR, ldr, Gr, nref, partials, ctx->num_cu);
-    launch_symmetrize(st, nref, Gr, nref);
-    sym_eig(st, nref, Gr, epsd, Yr, eigwork);
-    for (int c0 = 0; c0 < nref; c0 += 64) {
-      const int w = std::min(64, nref - c0);
-      launch_update(st, n, nref, w, 1.0, UR, ldr, Yr + c0, nref, 0.0, Urot + c0, ldr);
-    }
-    std::vector<double> eps(nref);
-    PF_HIP(hipMemcpyAsync(eps.data(), epsd, sizeof(double) * nref, hipMemcpyDeviceToHost, st));
-    PF_HIP(hipStreamSynchronize(st));
-    std::vector<double> E(nref);
-    for (int i = 0; i < nref; ++i) E[i] = (eps[i] - b) / a;
-    // the nev nearest sigma_H (ties -> lower E), ascending
-    std::vector<int> ord(nref);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
-      const double dx = std::fabs(E[x] - sigma_H), dy = std::fabs(E[y] - sigma_H);
-      if (dx != dy) return dx < dy;
-      return E[x] < E[y];
-    });
-    std::vector<int> sel(ord.begin(), ord.begin() + nout);
-    std::sort(sel.begin(), sel.end(), [&](int x, int y) { return E[x] < E[y]; });
-    for (int i = 0; i < nout; ++i) Esel[i] = E[sel[i]];
-    PF_HIP(hipMemcpyAsync(didx, sel.data(), sizeof(int) * nout, hipMemcpyHostToDevice, st));
-    launch_gather_cols(st, n, nout, Urot, ldr, didx, Vout, ldo);
-    // normalise, sign fix, residuals ||Hv - Ev|| with the unscaled H
+  // Vout (n x nout, ld ldo) <- columns idx of X (ld ldx); then normalise,
+  // fix signs and compute ||H v - E v||.  Returns the largest residual.
+  auto finish = [&](const double *X, long long ldx, const std::vector<int> &idx,
+                    const std::vector<double> &Ev) -> double {
+    nout = (int)idx.size();
+    Esel = Ev;
+    r.assign(nout, 0.0);
+    PF_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int) * nout, hipMemcpyHostToDevice, st));
+    launch_gather_cols(st, n, nout, X, ldx, didx, Vout, ldo);
     launch_colnorms(st, n, nout, Vout, ldo, nrm, partials, ctx->num_cu);
     std::vector<double> hn(nout);
     PF_HIP(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
@@ -728,44 +654,147 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
     PF_HIP(hipStreamSynchronize(st));
     double rmax = 0.0;
     for (int i = 0; i < nout; ++i) rmax = std::max(rmax, r[i]);
-    if (verbose)
-      fprintf(stderr, "[polfed] rr pass %d: K_r %lld, %d vectors, max resid / ||H|| = %.3e\n",
-              passes, passes ? K_r : 0LL, nref, rmax / normH);
-    if (!fp32 || rmax <= o.tol * normH || passes >= 4) break;
+    return rmax;
+  };
+  // indices of the k values of E nearest sigma_H (ties -> lower E), taken
+  // from those with ok[i]; returned ascending in E
+  auto nearest = [&](const std::vector<double> &E, const std::vector<char> &ok, int k) {
+    std::vector<int> ord;
+    for (int i = 0; i < (int)E.size(); ++i)
+      if (ok[i]) ord.push_back(i);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+      const double dx = std::fabs(E[x] - sigma_H), dy = std::fabs(E[y] - sigma_H);
+      if (dx != dy) return dx < dy;
+      return E[x] < E[y];
+    });
+    if ((int)ord.size() > k) ord.resize(k);
+    std::sort(ord.begin(), ord.end(), [&](int x, int y) { return E[x] < E[y]; });
+    return ord;
+  };
 
-    // FP64 refinement (FP32-filter mode): the FP32 rounding of the filter
-    // leaves broadband error components ~eps32 sqrt(K) in the Ritz vectors;
-    // an FP64 filter of order K_r damps a component at distance u (in the
-    // angle of x = cos u) from the target by ~1/(K_r u) while keeping the
-    // wanted ones near 1, and Rayleigh-Ritz on the filtered span removes the
-    // mixing.  Subspace iteration on the nout + margin vectors nearest the
-    // target; K_r = K/4, K/2, K, K on successive passes.
-    const double tr0 = now_s();
-    double *cheb64 = static_cast<double *>(ctx->buf("cheb64").ensure(sizeof(double) * 3 * (size_t)n * 64));
-    // refine the nout + margin Ritz vectors nearest the target: gather them
-    // (ordered by distance) to the front of Urot
-    const int q = std::min(nref, nout + std::max(8, nout / 4));
-    {
-      std::vector<int> near(ord.begin(), ord.begin() + q);
+  {
+    // candidates: theta >= p (else the nev largest theta); their Ritz vectors
+    // Qm t_i span the Rayleigh-Ritz space
+    std::vector<int> cand;
+    for (int i = 0; i < ms; ++i)
+      if (theta[i] >= o.p) cand.push_back(i);
+    if ((int)cand.size() < nev) {
+      cand.clear();
+      for (int i = ms - 1; i >= 0 && (int)cand.size() < nev; --i) cand.push_back(i);
+      std::sort(cand.begin(), cand.end());
+    }
+    const int nc = (int)cand.size();
+    // refined columns (FP32 mode): the nev + margin nearest, padded to whole
+    // kernel widths (a power of two up to 64, then multiples of 64) so that a
+    // short, launch-bound step moves as many columns as possible
+    const int q = std::min(nc, nev + std::max(8, nev / 4));
+    int qpad = 1;
+    while (qpad < q && qpad < 64) qpad *= 2;
+    if (q > 64) qpad = ((q + 63) / 64) * 64;
+    const int ldr = std::max(((nc + 7) / 8) * 8, qpad);
+    PF_HIP(hipMemcpyAsync(didx, cand.data(), sizeof(int) * nc, hipMemcpyHostToDevice, st));
+    double *Tsel = static_cast<double *>(ctx->buf("Tsel").ensure(sizeof(double) * (size_t)ms * ldr));
+    launch_gather_cols(st, ms, nc, Vt, ms, didx, Tsel, ldr);
+    double *UR = static_cast<double *>(ctx->buf("UR").ensure(sizeof(double) * (size_t)n * ldr));
+    double *WR = static_cast<double *>(ctx->buf("WR").ensure(sizeof(double) * (size_t)n * ldr));
+    for (int c0 = 0; c0 < nc; c0 += 64) {
+      const int w = std::min(64, nc - c0);
+      launch_update(st, n, ms, w, 1.0, Q, P, Tsel + c0, ldr, 0.0, UR + c0, ldr);
+    }
+    double *Gr = static_cast<double *>(ctx->buf("Gr").ensure(sizeof(double) * (size_t)ldr * ldr * 3 + 16));
+    double *Yr = Gr + (size_t)ldr * ldr;
+    double *Mr = Yr + (size_t)ldr * ldr;
+    double *epsd = static_cast<double *>(ctx->buf("epsd").ensure(sizeof(double) * (size_t)ldr));
+    std::vector<double> E;
+    std::vector<int> sel;
+    // Rayleigh-Ritz of H~ on span(UR[:, :k]) (orthonormal): WR = UR Y
+    auto rayleigh_ritz = [&](int k) {
+      apply_op<double>(ctx, c, dt64, 0.5 * a * c.J1, 0.5 * a * c.J2, UR, ldr, WR, ldr, k, false);
+      rr_apps += k;
+      launch_gram(st, n, k, k, UR, ldr, WR, ldr, Gr, k, partials, ctx->num_cu);
+      launch_symmetrize(st, k, Gr, k);
+      sym_eig(st, k, Gr, epsd, Yr, eigwork);
+      for (int c0 = 0; c0 < k; c0 += 64) {
+        const int w = std::min(64, k - c0);
+        launch_update(st, n, k, w, 1.0, UR, ldr, Yr + c0, k, 0.0, WR + c0, ldr);
+      }
+      std::vector<double> eps(k);
+      PF_HIP(hipMemcpyAsync(eps.data(), epsd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+      PF_HIP(hipStreamSynchronize(st));
+      E.resize(k);
+      for (int i = 0; i < k; ++i) E[i] = (eps[i] - b) / a;
+      sel = nearest(E, std::vector<char>(k, 1), nev);
+      std::vector<double> Ev;
+      for (int i : sel) Ev.push_back(E[i]);
+      return finish(WR, ldr, sel, Ev);
+    };
+    double rmax = rayleigh_ritz(nc);
+    if (verbose) fprintf(stderr, "[polfed] rr: %d candidates, max resid / ||H|| = %.3e\n", nc, rmax / normH);
+
+    // FP64 refinement of the FP32-filter mode.  The FP32 rounding of the
+    // recurrence leaves errors ~eps32 sqrt(K) in the Ritz vectors, largest
+    // along eigenvectors whose theta is close to theta_i.  Subspace iteration
+    // with the FP64 filter P^{K_r}(H~) on the nearest q Ritz vectors damps a
+    // component at angular distance u from the target by ~1/(K_r u) relative
+    // to the wanted ones (near-window components by theta_k / theta_i), and
+    // Rayleigh-Ritz on the filtered span removes the mixing; K_r = K/4, K/2,
+    // K, K.  Target: 2e-9 ||H|| (or tol if looser), 5x under the 1e-8 ||H||
+    // bar for returned residuals.
+    const double target = std::max(o.tol, 2e-9) * normH;
+    long long K_r = std::max<long long>(16, K / 4);
+    std::vector<double> coef_r;
+    double D_r = 1.0;
+    double *Vn = static_cast<double *>(ctx->buf("Vn").ensure(sizeof(double) * (size_t)n * ldr));
+    double *cheb64 = nullptr;
+    bool zeroed = false;
+    while (fp32 && rmax > target && passes < 4) {
+      const double tr0 = now_s();
+      if (!cheb64)
+        cheb64 = static_cast<double *>(ctx->buf("cheb64").ensure(sizeof(double) * 3 * (size_t)n * 64));
+      if (!zeroed) {  // padding columns stay zero
+        launch_fill(st, Vn, (long long)n * ldr, 0.0);
+        zeroed = true;
+      }
+      std::vector<int> near = nearest(E, std::vector<char>(E.size(), 1), q);
       PF_HIP(hipMemcpyAsync(didx, near.data(), sizeof(int) * q, hipMemcpyHostToDevice, st));
-      launch_gather_cols(st, n, q, Urot, ldr, didx, WR, ldr);
+      launch_gather_cols(st, n, q, WR, ldr, didx, Vn, ldr);
+      cheb_coeffs(sigma, K_r, coef_r, D_r);
+      for (int c0 = 0; c0 < qpad; c0 += 64) {
+        const int w = std::min(64, qpad - c0);
+        run_filter<double>(ctx, c, dt64, a, w, Vn + c0, ldr, UR + c0, ldr, K_r, coef_r, D_r, cheb64,
+                           false, &refine_bytes);
+      }
+      rr_apps += (double)(K_r + 1) * q;
+      // SVQB orthonormalisation of UR[:, :q] (twice): UR <- UR W Lambda^{-1/2}
+      for (int it = 0; it < 2; ++it) {
+        launch_gram(st, n, q, q, UR, ldr, UR, ldr, Gr, q, partials, ctx->num_cu);
+        launch_symmetrize(st, q, Gr, q);
+        sym_eig(st, q, Gr, epsd, Yr, eigwork);
+        std::vector<double> lam(q), W((size_t)q * q);
+        PF_HIP(hipMemcpyAsync(lam.data(), epsd, sizeof(double) * q, hipMemcpyDeviceToHost, st));
+        PF_HIP(hipMemcpyAsync(W.data(), Yr, sizeof(double) * q * q, hipMemcpyDeviceToHost, st));
+        PF_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < q; ++i) {
+          const double f = (lam[i] > 1e-28 * lam[q - 1]) ? 1.0 / std::sqrt(lam[i]) : 0.0;
+          for (int k = 0; k < q; ++k) W[(size_t)k * q + i] *= f;
+        }
+        PF_HIP(hipMemcpyAsync(Mr, W.data(), sizeof(double) * q * q, hipMemcpyHostToDevice, st));
+        for (int c0 = 0; c0 < q; c0 += 64) {
+          const int w = std::min(64, q - c0);
+          launch_update(st, n, q, w, 1.0, UR, ldr, Mr + c0, q, 0.0, WR + c0, ldr);
+        }
+        PF_HIP(hipMemcpy2DAsync(UR, sizeof(double) * ldr, WR, sizeof(double) * ldr,
+                                sizeof(double) * q, n, hipMemcpyDeviceToDevice, st));
+      }
+      PF_HIP(hipStreamSynchronize(st));
+      t_refine += now_s() - tr0;
+      ++passes;
+      rmax = rayleigh_ritz(q);
+      if (verbose)
+        fprintf(stderr, "[polfed] refine pass %d: K_r %lld, %d vectors, max resid / ||H|| = %.3e\n",
+                passes, K_r, q, rmax / normH);
+      K_r = std::min<long long>(2 * K_r, K);
     }
-    const std::vector<double> &cr = coef_r(K_r, sigma);
-    for (int c0 = 0; c0 < q;) {
-      int w = 64;
-      while (w > q - c0) w >>= 1;
-      run_filter<double>(ctx, c, dt64, a, w, WR + c0, ldr, UR + c0, ldr, K_r, cr, D_r, cheb64,
-                         false, &refine_bytes);
-      c0 += w;
-    }
-    nref = q;
-    svqb(UR, ldr, nref);
-    svqb(UR, ldr, nref);
-    PF_HIP(hipStreamSynchronize(st));
-    t_refine += now_s() - tr0;
-    rr_apps += (double)(K_r + 1) * nref;
-    ++passes;
-    K_r = std::min<long long>(2 * K_r, K);
   }
   if (evecs) {
     double *cm = static_cast<double *>(ctx->buf("colmajor").ensure(sizeof(double) * (size_t)n * nout));

@@ -1,0 +1,136 @@
+"""Profiling driver for the Chebyshev step kernel (run under rocprofv3).
+
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- \
+        python -m paper_2005_09534_amd.profile_kernels run --workload c2
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT -o write -- \
+        python -m paper_2005_09534_amd.profile_kernels run --workload c2
+    python -m paper_2005_09534_amd.profile_kernels summarize --workload c2 \
+        --fetch OUT/.../fetch_counter_collection.csv --write OUT/.../write_counter_collection.csv \
+        > profiles/k_step_c2_traffic.txt
+
+``run`` applies the workload's filter (its chain, block width and precision)
+for a fixed number of steps, then copies a buffer of known size with a plain
+device-to-device copy kernel, whose counter readings calibrate the byte
+counts.  ``summarize`` turns the two counter CSVs into HBM bytes per step
+launch and records the hash of the kernel source the counters were taken on.
+"""
+
+import argparse
+import csv
+import hashlib
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_2005_09534_amd", "csrc", "hv.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _workload(name):
+    from paper_2005_09534_amd import workloads
+    return {"c1": workloads.c1, "c2": workloads.c2, "c3_fp64": lambda: workloads.c3("fp64"),
+            "c3_fp32": lambda: workloads.c3("fp32"), "c5": workloads.c5}[name]()
+
+
+def run(args):
+    import torch
+    from paper_2005_09534_amd import polfed as pf
+    wl = _workload(args.workload)
+    c = wl.chains[0]
+    ctx = pf.Context(0)
+    m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
+    n = pf.dim(c.L)
+    s = wl.block if wl.block > 0 else 16
+    dt = torch.float32 if wl.precision == "fp32" else torch.float64
+    # the operator of the solve: Lanczos bounds widened as the solver does,
+    # target at the workload's rescaled energy
+    E0, E1, r0, r1 = ctx.bounds(m, 200)
+    w = E1 - E0
+    E0w, E1w = E0 - r0 - 1e-3 * w, E1 + r1 + 1e-3 * w
+    sigma_H = E0 + wl.eps_target * w
+    sigma = (2.0 * sigma_H - (E0w + E1w)) / (E1w - E0w)
+    X = torch.randn((n, s), device="cuda", dtype=torch.float64).to(dt)
+    Y = torch.empty_like(X)
+    ctx.set_graphs(False)  # one dispatch per step, each counted
+    ctx.apply_filter(m, E0w, E1w, sigma, args.K, X, out=Y)
+    torch.cuda.synchronize()
+    st = ctx.filter_stats(reset=True)
+    # calibration: a plain copy of COPY_BYTES bytes
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"filter: {st['launches']:.0f} launches, {st['bytes'] / st['launches']:.0f} algorithmic "
+          f"bytes/launch, {1e6 * st['gpu_s'] / st['launches']:.2f} us/launch (HIP events)")
+    ctx.close()
+
+
+def _read(path, counter, step_name):
+    """(per-dispatch values of `counter` for the step kernel instantiation
+    `step_name`, largest value for the runtime's device-to-device copy
+    kernel) from a rocprofv3 counter_collection CSV."""
+    step, copy = [], []
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name") or ""
+            if row.get("Counter_Name", counter) != counter:
+                continue
+            v = float(row.get("Counter_Value") or 0.0)
+            if step_name in name:
+                step.append(v)
+            elif "copyBuffer" in name:
+                copy.append(v)
+    return step, (max(copy) if copy else 0.0)
+
+
+def summarize(args):
+    wl = _workload(args.workload)
+    T = "float" if wl.precision == "fp32" else "double"
+    s = wl.block if wl.block > 0 else 16
+    step_name = f"k_step<{T}, {s},"
+    fs, fc = _read(args.fetch, "FETCH_SIZE", step_name)
+    ws, wc = _read(args.write, "WRITE_SIZE", step_name)
+    if not fs or not ws or not fc or not wc:
+        sys.exit("missing step or copy dispatches in the counter files")
+    # the copy kernel reads and writes COPY_BYTES: scale KiB readings to bytes
+    kf = COPY_BYTES / (fc * 1024.0)
+    kw = COPY_BYTES / (wc * 1024.0)
+    fetch = sum(fs) / len(fs) * 1024.0 * kf
+    write = sum(ws) / len(ws) * 1024.0 * kw
+    print(f"# HBM traffic of the Chebyshev step kernel ({step_name}...>), workload {args.workload}")
+    print("# counters: rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE (KiB per dispatch),")
+    print("# each scaled by its reading for a device-to-device copy of COPY_BYTES bytes")
+    print(f"# calibration: a {COPY_BYTES} B copy read {fc:.0f} KiB and wrote {wc:.0f} KiB")
+    print(f"workload = {args.workload}")
+    print(f"dispatches = {len(fs)}")
+    print(f"fetch_kib_per_launch_raw = {sum(fs) / len(fs):.1f}")
+    print(f"write_kib_per_launch_raw = {sum(ws) / len(ws):.1f}")
+    print(f"fetch_scale = {kf:.4f}")
+    print(f"write_scale = {kw:.4f}")
+    print(f"hbm_fetch_bytes_per_launch = {fetch:.0f}")
+    print(f"hbm_write_bytes_per_launch = {write:.0f}")
+    print(f"hbm_bytes_per_launch = {fetch + write:.0f}")
+    print(f"kernel_source_sha256_16 = {kernel_source_hash()}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--workload", default="c2")
+    r.add_argument("--K", type=int, default=64)
+    s = sub.add_parser("summarize")
+    s.add_argument("--workload", default="c2")
+    s.add_argument("--fetch", required=True)
+    s.add_argument("--write", required=True)
+    a = ap.parse_args()
+    sys.path.insert(0, ROOT)
+    run(a) if a.cmd == "run" else summarize(a)
+
+
+if __name__ == "__main__":
+    main()

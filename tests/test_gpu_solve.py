@@ -177,22 +177,26 @@ def test_solve_c2_vs_golden(ctx, pf):
 
 
 def test_solve_fp32_filter_small(ctx, pf):
-    """FP32 filter + FP64 Lanczos / Rayleigh-Ritz on a dense-checkable chain."""
-    c = workloads.chain(14, 3.0, 321)
-    H = chain.hamiltonian_csr(14, c.J1, c.J2, c.Delta, c.h)
+    """FP32 filter + FP64 Lanczos / Rayleigh-Ritz / refinement on a
+    dense-checkable chain (L=16, 12,870 states, 40 pairs, s=16)."""
+    c = workloads.chain(16, 3.0, 337)
+    H = chain.hamiltonian_csr(16, c.J1, c.J2, c.Delta, c.h)
     E0, E1 = lanczos.extreme_eigenvalues(H)
     sigma = E0 + 0.5 * (E1 - E0)
-    m = pf.make_model(14, c.J1, c.J2, c.Delta, c.h)
-    res = ctx.solve(m, 20, block_size=8, precision=1, target_kind=1, target=sigma)
+    m = pf.make_model(16, c.J1, c.J2, c.Delta, c.h)
+    res = ctx.solve(m, 40, block_size=16, precision=1, target_kind=1, target=sigma)
     info = res["info"]
     print("fp32 info", {k: info[k] for k in ("K", "m", "n_conv", "max_resid", "refine_passes")})
     w = dense.full_spectrum(H)
-    Ed = w[dense.nearest_from_spectrum(w, sigma, 20)]
+    Ed = w[dense.nearest_from_spectrum(w, sigma, 40)]
     normH = max(abs(E0), abs(E1))
     print("fp32 max |dE|/||H||", np.abs(res["E"] - Ed).max() / normH, "max resid/||H||",
           res["resid"].max() / normH)
+    assert res["status"] == pf.OK
     assert np.abs(res["E"] - Ed).max() <= 1e-10 * normH
     assert res["resid"].max() <= 1e-8 * normH
+    r = np.linalg.norm(H @ res["V"] - res["V"] * res["E"], axis=0)
+    assert r.max() <= 1e-8 * normH
 
 
 def test_solve_deterministic(ctx, pf):
