@@ -74,7 +74,7 @@ typedef struct {
                              Rayleigh-Ritz and residuals + FP64 refinement  */
   double window_factor;   /* filter window sized for ceil(f N_ev)
                              eigenvalues; 0 -> 1.5                          */
-  int max_cols;           /* Lanczos columns; 0 -> 4 N_win + 6 s           */
+  int max_cols;           /* Lanczos columns; 0 -> 6 N_win + 6 s           */
   double tol;             /* residual target relative to ||H||; 0 -> 1e-10 */
   double eta;             /* bounds margin, fraction of E1-E0; 0 -> 1e-3   */
   int bounds_steps;       /* bounds Lanczos steps; 0 -> 200                 */
@@ -93,7 +93,9 @@ typedef struct {
   int block_size;         /* s used                                         */
   int m;                  /* Lanczos blocks at stop                         */
   int n_conv;             /* pairs with residual <= tol ||H||              */
-  int refine_passes;      /* FP64 refinement passes (precision 1)           */
+  int refine_passes;      /* FP64 refinement passes (precision 1); -1 when
+                             the FP32 result missed 1e-8 ||H|| and was
+                             recomputed with the FP64 filter               */
   double max_resid;       /* max returned residual (H units)                */
   double t_bounds, t_filter, t_orth, t_eig, t_rr, t_refine, t_total;
   double hv_apps;         /* H~ applications to single vectors              */

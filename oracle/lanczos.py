@@ -18,7 +18,8 @@ Main text "POLFED algorithm" and Supplement "Convergence of POLFED":
 6. T_m block tridiagonal: A_j on the diagonal, B_{j+1} below, B_{j+1}^T above;
 7. eigenpairs (theta_i, t_i) of T_m; an eigenpair with theta_i >= p is
    converged when ||B_{j+1} t~_i|| <= tau (t~_i: last s entries of t_i);
-   stop once the count reaches N_ev;
+   stop once the count reaches N_ev (reading: if fewer than N_ev Ritz values
+   exceed p, the N_ev largest theta take their place);
 8. Ritz vectors u_i = Qm t_i for theta_i >= p, Rayleigh-Ritz of H~ on their
    span (this reduces to eps_i = u_i^T H~ u_i when the theta are distinct;
    P is locally even around sigma, so pairs sigma +- d share theta and the
@@ -109,6 +110,11 @@ def block_lanczos(H, E0w, E1w, sigma_t, K, nev, s, p=0.17, tau=1e-10,
         theta, t = np.linalg.eigh(T)
         res = np.linalg.norm(B @ t[-s:, :], axis=0)
         sel = theta >= p
+        if sel.sum() < nev:
+            # reading: the Gaussian DOS can overestimate the window, leaving
+            # fewer than N_ev Ritz values above p; then the N_ev largest theta
+            # are the ones that must converge
+            sel = theta >= np.sort(theta)[::-1][min(nev, len(theta)) - 1]
         nconv = int(np.sum(sel & (res <= tau)))
         result = dict(Qm=np.hstack(Qs), T=T, theta=theta, t=t, res=res, sel=sel,
                       nconv=nconv, m=m, B_last=B)
@@ -168,12 +174,14 @@ def window_count(nev, factor=1.5):
 
 
 def column_cap(nwin, s):
-    """Lanczos columns allocated: 4 N_win + 6s, in whole blocks.  The paper
+    """Lanczos columns allocated: 6 N_win + 6s, in whole blocks.  The paper
     allocates 2.8 N_ev columns, a bound it states for s <= 24 and
     N_ev >= 1000; at the N_ev = 8..100 of the workloads here convergence
-    was observed to need up to ~5 N_ev columns with s = 4, and ~12 blocks
-    when s is as large as N_ev."""
-    cols = 4 * nwin + 6 * s
+    was observed to need up to ~5 N_ev columns with s = 4, ~12 blocks when s
+    is as large as N_ev, and more when the window holds fewer than N_ev
+    eigenvalues above p (Gaussian DOS overestimated) and the N_ev-th must
+    converge from below p."""
+    cols = 6 * nwin + 6 * s
     return -(-cols // s) * s
 
 

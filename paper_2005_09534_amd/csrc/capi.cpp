@@ -13,6 +13,9 @@ namespace polfed {
 void make_chain(polfed_ctx *ctx, const polfed_model *m, Chain &c);
 int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opts, int nev,
               double *evals, double *evecs, double *resid, polfed_info *info);
+int solve_batch(polfed_ctx *ctx, int R, const polfed_model *models, const polfed_opts *opts,
+                int nev, double *evals, double *evecs, double *resid, polfed_info *infos,
+                int *status);
 void run_bounds(polfed_ctx *ctx, const Chain &c, int steps, unsigned long long seed, double &E0,
                 double &E1, double &r0, double &r1);
 template <class T>
@@ -370,19 +373,7 @@ int polfed_solve_batch(polfed_ctx *ctx, int R, const polfed_model *models,
                        const polfed_opts *opts, int nev, double *evals, double *evecs,
                        double *resid, polfed_info *infos, int *status) {
   return guarded(ctx, [&] {
-    PF_REQUIRE(R >= 1 && models && status && evals && resid, "invalid batch arguments");
-    int worst = POLFED_OK;
-    size_t off = 0;
-    for (int r = 0; r < R; ++r) {
-      int rc = solve_one(ctx, &models[r], opts, nev, evals + (size_t)r * nev,
-                         evecs ? evecs + off : nullptr, resid + (size_t)r * nev,
-                         infos ? infos + r : nullptr);
-      status[r] = rc;
-      if (rc < 0 && worst >= 0) worst = rc;
-      if (rc > 0 && worst == POLFED_OK) worst = rc;
-      off += (size_t)polfed_dim(models[r].L) * nev;
-    }
-    return worst;
+    return solve_batch(ctx, R, models, opts, nev, evals, evecs, resid, infos, status);
   });
 }
 

@@ -18,11 +18,13 @@
 // Layout: blocks are row-major (the s values of a row contiguous), so one
 // gathered neighbour is one contiguous s * sizeof(T) segment.  A row is
 // owned by G lanes, each moving VEC = 16/sizeof(T) * LPL elements with 16-byte
-// vector loads; 64/G rows share a wavefront.  Workgroups are persistent and
-// each owns a contiguous range of rows; the workgroup index is remapped so
-// that the ranges of one XCD are adjacent (consecutive workgroup ids land on
-// different XCDs), which keeps the near-diagonal gathers inside one L2.
-// The rank tables are staged in LDS once per workgroup.
+// vector loads; 64/G rows share a wavefront.  Workgroups are persistent;
+// each XCD sweeps one contiguous eighth of the rows with all its groups in
+// step (see the tile schedule below), which keeps the gathers of a row's
+// own bit segment inside that XCD's L2.  The rank tables are staged in LDS
+// once per workgroup.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace polfed {
@@ -53,6 +55,20 @@ __device__ __forceinline__ void load_row(const T *__restrict__ p, T (&v)[VEC]) {
   }
 }
 
+// Streaming rows (X, W in, the output out) are touched once per step:
+// non-temporal accesses keep them from displacing the gathered block in L2.
+template <class T, int VEC, int LDV>
+__device__ __forceinline__ void load_row_nt(const T *__restrict__ p, T (&v)[VEC]) {
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) v[k] = __builtin_nontemporal_load(p + k);
+}
+
+template <class T, int VEC, int LDV>
+__device__ __forceinline__ void store_row_nt(T *__restrict__ p, const T (&v)[VEC]) {
+#pragma unroll
+  for (int k = 0; k < VEC; ++k) __builtin_nontemporal_store(v[k], p + k);
+}
+
 template <class T, int VEC, int LDV>
 __device__ __forceinline__ void store_row(T *__restrict__ p, const T (&v)[VEC]) {
 #pragma unroll
@@ -71,118 +87,216 @@ struct Chunk {
   static constexpr int value = (32 / VEC) > 8 ? 8 : ((32 / VEC) < 2 ? 2 : 32 / VEC);
 };
 
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
+// One row of the fused step: out[r,:] for the lanes (col .. col+VEC) this
+// thread owns.  tA / tB are the rank tables (LDS or global).
+template <class T, int S, int LPL>
+__device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int col,
+                                         const int32_t *__restrict__ tA,
+                                         const int32_t *__restrict__ tB) {
   using C = StepCfg<T, S, LPL>;
-  constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW, LDV = C::LDV;
+  constexpr int VEC = C::VEC, LDV = C::LDV;
   constexpr int kChunk = Chunk<VEC>::value;
-  extern __shared__ int32_t s_tab[];
-
-  const int32_t *tA = a.tabA;
-  const int32_t *tB = a.tabB;
-  const int tsz = 1 << a.half;
-  if (LDS_TAB) {
-    for (int i = threadIdx.x; i < tsz; i += blockDim.x) {
-      s_tab[i] = a.tabA[i];
-      s_tab[tsz + i] = a.tabB[i];
-    }
-    __syncthreads();
-    tA = s_tab;
-    tB = s_tab + tsz;
-  }
-
-  // XCD-aware remap: physical id b runs on XCD b % 8; give each XCD one
-  // contiguous run of logical ranges.
-  const unsigned nwg = gridDim.x;
-  const unsigned b = blockIdx.x;
-  unsigned logical = b;
-  if ((nwg & 7u) == 0u) logical = (b & 7u) * (nwg >> 3) + (b >> 3);
-
-  const long long r_begin = (long long)logical * a.rows_per_wg;
-  long long r_end = r_begin + a.rows_per_wg;
-  if (r_end > a.n) r_end = a.n;
-
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int slot = lane / G;
-  const int col = (lane % G) * VEC;
-  const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
   const int L = a.L;
   const uint32_t fullmask = a.fullmask;
   const uint32_t lomask = a.lomask;
   const int half = a.half;
 
-  for (long long base = r_begin; base < r_end; base += rows_per_iter) {
-    const long long r = base + (long long)wave * RPW + slot;
-    if (r >= r_end) continue;
-
-    T acc[VEC];
+  T acc[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+  for (int e = 0; e < VEC; ++e) acc[e] = T(0);
 
-    if (a.V != nullptr) {
-      const uint32_t s = a.states[r];
-      T self[VEC];
-      load_row<T, VEC, LDV>(a.V + (size_t)r * a.ldv + col, self);
-      const T dd = a.dscale * a.dt[r];
+  if (a.V != nullptr) {
+    const uint32_t s = a.states[r];
+    T self[VEC];
+    load_row<T, VEC, LDV>(a.V + (size_t)r * a.ldv + col, self);
+    const T dd = a.dscale * a.dt[r];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[e] = dd * self[e];
+    for (int e = 0; e < VEC; ++e) acc[e] = dd * self[e];
 
-      // antiparallel bonds: bit i of s ^ rot_l(s) marks the pair (i, i+l)
-      const uint32_t rot1 = ((s >> 1) | (s << (L - 1))) & fullmask;
-      unsigned long long mm = (unsigned long long)(s ^ rot1);
-      if (a.has_j2) {
-        const uint32_t rot2 = ((s >> 2) | (s << (L - 2))) & fullmask;
-        mm |= (unsigned long long)(s ^ rot2) << 32;
+    // antiparallel bonds: bit i of s ^ rot_l(s) marks the pair (i, i+l)
+    const uint32_t rot1 = ((s >> 1) | (s << (L - 1))) & fullmask;
+    unsigned long long mm = (unsigned long long)(s ^ rot1);
+    if (a.has_j2) {
+      const uint32_t rot2 = ((s >> 2) | (s << (L - 2))) & fullmask;
+      mm |= (unsigned long long)(s ^ rot2) << 32;
+    }
+    while (mm) {
+      int32_t idx[kChunk];
+      bool two[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        idx[u] = -1;
+        two[u] = false;
+        if (mm) {
+          const int bit = __ffsll((long long)mm) - 1;
+          mm &= mm - 1ull;
+          const int l = (bit >= 32) ? 2 : 1;
+          const int i = bit & 31;
+          int j = i + l;
+          if (j >= L) j -= L;
+          const uint32_t f = s ^ ((1u << i) | (1u << j));
+          idx[u] = tA[f >> half] + tB[f & lomask];
+          two[u] = (l == 2);
+        }
       }
-      while (mm) {
-        int32_t idx[kChunk];
-        bool two[kChunk];
+      T nb[kChunk][VEC];
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-          idx[u] = -1;
-          two[u] = false;
-          if (mm) {
-            const int bit = __ffsll((long long)mm) - 1;
-            mm &= mm - 1ull;
-            const int l = (bit >= 32) ? 2 : 1;
-            const int i = bit & 31;
-            int j = i + l;
-            if (j >= L) j -= L;
-            const uint32_t f = s ^ ((1u << i) | (1u << j));
-            idx[u] = tA[f >> half] + tB[f & lomask];
-            two[u] = (l == 2);
-          }
-        }
-        T nb[kChunk][VEC];
+      for (int u = 0; u < kChunk; ++u) {
+        if (idx[u] >= 0) load_row<T, VEC, LDV>(a.V + (size_t)idx[u] * a.ldv + col, nb[u]);
+      }
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-          if (idx[u] >= 0) load_row<T, VEC, LDV>(a.V + (size_t)idx[u] * a.ldv + col, nb[u]);
-        }
+      for (int u = 0; u < kChunk; ++u) {
+        if (idx[u] >= 0) {
+          const T w = two[u] ? a.w2 : a.w1;
 #pragma unroll
-        for (int u = 0; u < kChunk; ++u) {
-          if (idx[u] >= 0) {
-            const T w = two[u] ? a.w2 : a.w1;
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[e] += w * nb[u][e];
-          }
+          for (int e = 0; e < VEC; ++e) acc[e] += w * nb[u][e];
         }
       }
     }
+  }
 
-    if (a.X != nullptr) {
-      T x[VEC];
-      load_row<T, VEC, LDV>(a.X + (size_t)r * a.ldx + col, x);
+  if (a.X != nullptr) {
+    T x[VEC];
+    load_row_nt<T, VEC, LDV>(a.X + (size_t)r * a.ldx + col, x);
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[e] += a.alpha * x[e];
-    }
-    if (a.W != nullptr) {
-      T w[VEC];
-      load_row<T, VEC, LDV>(a.W + (size_t)r * a.ldw + col, w);
+    for (int e = 0; e < VEC; ++e) acc[e] += a.alpha * x[e];
+  }
+  if (a.W != nullptr) {
+    T w[VEC];
+    load_row_nt<T, VEC, LDV>(a.W + (size_t)r * a.ldw + col, w);
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) acc[e] += a.gamma * w[e];
+    for (int e = 0; e < VEC; ++e) acc[e] += a.gamma * w[e];
+  }
+  store_row_nt<T, VEC, LDV>(a.out + (size_t)r * a.ldo + col, acc);
+}
+
+// Stage the two rank tables in LDS (when LDS_TAB) and return their bases.
+template <bool LDS_TAB>
+__device__ __forceinline__ void stage_tables(const int32_t *gA, const int32_t *gB, int half,
+                                             int32_t *s_tab, const int32_t *&tA,
+                                             const int32_t *&tB) {
+  tA = gA;
+  tB = gB;
+  if (LDS_TAB) {
+    const int tsz = 1 << half;
+    for (int i = threadIdx.x; i < tsz; i += blockDim.x) {
+      s_tab[i] = gA[i];
+      s_tab[tsz + i] = gB[i];
     }
-    store_row<T, VEC, LDV>(a.out + (size_t)r * a.ldo + col, acc);
+    __syncthreads();
+    tA = s_tab;
+    tB = s_tab + tsz;
+  }
+}
+
+// Tile range of physical group b of nwg over ntiles tiles.  Physical group b
+// runs on XCD b % 8 (groups are dealt to the XCDs round-robin); XCD x owns
+// the contiguous tile range [x TX, (x+1) TX) and its W = nwg/8 groups stride
+// through it together, so the rows in flight on one XCD form one contiguous
+// window: the neighbours a row gathers from its own bit segment (and, in a
+// batch, its own realisation) are then mostly in that XCD's L2.
+__device__ __forceinline__ void xcd_tiles(long long ntiles, long long &t_begin, long long &t_end,
+                                          long long &t_step) {
+  const unsigned nwg = gridDim.x;
+  const unsigned b = blockIdx.x;
+  if ((nwg & 7u) == 0u) {
+    const long long W = nwg >> 3;
+    const long long TX = (ntiles + 7) / 8;
+    const long long x = b & 7u, slot_g = b >> 3;
+    t_begin = x * TX + slot_g;
+    t_end = (x + 1) * TX < ntiles ? (x + 1) * TX : ntiles;
+    t_step = W;
+  } else {
+    t_begin = b;
+    t_end = ntiles;
+    t_step = nwg;
+  }
+}
+
+template <class T, int S, int LPL, bool LDS_TAB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
+  using C = StepCfg<T, S, LPL>;
+  constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
+  extern __shared__ int32_t s_tab[];
+  const int32_t *tA, *tB;
+  stage_tables<LDS_TAB>(a.tabA, a.tabB, a.half, s_tab, tA, tB);
+
+  const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
+  const long long ntiles = (a.n + rows_per_iter - 1) / rows_per_iter;
+  long long t_begin, t_end, t_step;
+  xcd_tiles(ntiles, t_begin, t_end, t_step);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int slot = lane / G;
+  const int col = (lane % G) * VEC;
+  for (long long t = t_begin; t < t_end; t += t_step) {
+    const long long r = t * rows_per_iter + (long long)wave * RPW + slot;
+    if (r >= a.n) continue;
+    step_row<T, S, LPL>(a, r, col, tA, tB);
+  }
+}
+
+// Batched Clenshaw step for B realisations of one chain length L (same
+// basis, block width S): realisation i has its own diagonal, coefficients,
+// order K_i and buffers.  At global step j (0 <= j <= Kmax), realisation i
+// is at local step j_i = j - (Kmax - K_i) (idle while j_i < 0), so that all
+// end together; step Kmax is the final combination Y = (c_0 X + H~ b_1 -
+// b_2)/D.  Tiles run realisation-major, so an XCD works through whole
+// realisations.
+template <class T, int S, int LPL, bool LDS_TAB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const BatchItem<T> *items,
+                                                       int B, long long j, long long Kmax) {
+  using C = StepCfg<T, S, LPL>;
+  constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
+  extern __shared__ int32_t s_tab[];
+  const int32_t *tA, *tB;
+  stage_tables<LDS_TAB>(base.tabA, base.tabB, base.half, s_tab, tA, tB);
+
+  const long long n = base.n;
+  const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
+  const long long tper = (n + rows_per_iter - 1) / rows_per_iter;
+  long long t_begin, t_end, t_step;
+  xcd_tiles(tper * B, t_begin, t_end, t_step);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int slot = lane / G;
+  const int col = (lane % G) * VEC;
+  for (long long t = t_begin; t < t_end; t += t_step) {
+    const int i = (int)(t / tper);
+    const BatchItem<T> it = items[i];
+    const long long ji = j - (Kmax - it.K);
+    if (!it.active || ji < 0) continue;
+    const long long r = (t - (long long)i * tper) * rows_per_iter + (long long)wave * RPW + slot;
+    if (r >= n) continue;
+    StepArgs<T> a = base;
+    a.dt = it.dt;
+    const size_t blk = (size_t)n * S;
+    T *bufs[3] = {it.buf, it.buf + blk, it.buf + 2 * blk};
+    a.ldv = a.ldw = a.ldo = a.ldx = S;
+    if (j < Kmax) {
+      const long long k = it.K - ji;
+      a.out = bufs[ji % 3];
+      a.V = (ji >= 1) ? bufs[(ji - 1) % 3] : nullptr;
+      a.W = (ji >= 2) ? bufs[(ji - 2) % 3] : nullptr;
+      const double ck = it.coef[k];
+      a.X = (ck != 0.0) ? it.X : nullptr;
+      a.alpha = (T)ck;
+      a.dscale = T(2);
+      a.w1 = it.w1;
+      a.w2 = it.w2;
+      a.gamma = T(-1);
+    } else {
+      a.out = it.Y;
+      a.X = it.X;
+      a.alpha = (T)(it.coef[0] * it.Dinv);
+      a.V = (it.K >= 1) ? bufs[(it.K - 1) % 3] : nullptr;
+      a.W = (it.K >= 2) ? bufs[(it.K - 2) % 3] : nullptr;
+      a.dscale = (T)it.Dinv;
+      a.w1 = (T)(0.5 * (double)it.w1 * it.Dinv);
+      a.w2 = (T)(0.5 * (double)it.w2 * it.Dinv);
+      a.gamma = (T)(-it.Dinv);
+    }
+    step_row<T, S, LPL>(a, r, col, tA, tB);
   }
 }
 
@@ -194,13 +308,12 @@ static void launch_step_s(hipStream_t st, const StepArgs<T> &a0, const StepShape
   const int threads = shape.threads;
   const long long rows_per_iter = (long long)(threads / 64) * C::RPW;
   long long want = (long long)num_cu * shape.wg_per_cu;
-  long long iters_total = (a.n + rows_per_iter - 1) / rows_per_iter;
-  long long iters_per_wg = (iters_total + want - 1) / want;
-  if (iters_per_wg < 1) iters_per_wg = 1;
-  a.rows_per_wg = iters_per_wg * rows_per_iter;
-  long long nwg = (a.n + a.rows_per_wg - 1) / a.rows_per_wg;
-  // a multiple of 8 lets the kernel apply its XCD remap; extra groups exit
+  long long tiles = (a.n + rows_per_iter - 1) / rows_per_iter;
+  long long nwg = std::min(want, tiles);
+  // a multiple of 8 lets the kernel apply its per-XCD schedule; extra
+  // groups find no tile and exit
   nwg = ((nwg + 7) / 8) * 8;
+  a.rows_per_wg = rows_per_iter;
   const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
   size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
   if (threads > 256) {
@@ -217,6 +330,32 @@ static void launch_step_s(hipStream_t st, const StepArgs<T> &a0, const StepShape
       k_step<T, S, LPL, false, 256><<<(unsigned)nwg, threads, 0, st>>>(a);
   }
   check_launch("k_step");
+}
+
+template <class T, int S, int LPL>
+static void launch_batched_s(hipStream_t st, const StepArgs<T> &a, const BatchItem<T> *items,
+                             int B, long long j, long long Kmax, const StepShape &shape,
+                             int num_cu) {
+  using C = StepCfg<T, S, LPL>;
+  const int threads = shape.threads;
+  const long long rows_per_iter = (long long)(threads / 64) * C::RPW;
+  const long long tiles = ((a.n + rows_per_iter - 1) / rows_per_iter) * B;
+  long long nwg = std::min((long long)num_cu * shape.wg_per_cu, tiles);
+  nwg = ((nwg + 7) / 8) * 8;
+  const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
+  size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
+  if (threads > 256) {
+    if (lds)
+      k_step_batched<T, S, LPL, true, 1024><<<(unsigned)nwg, threads, shm, st>>>(a, items, B, j, Kmax);
+    else
+      k_step_batched<T, S, LPL, false, 1024><<<(unsigned)nwg, threads, 0, st>>>(a, items, B, j, Kmax);
+  } else {
+    if (lds)
+      k_step_batched<T, S, LPL, true, 256><<<(unsigned)nwg, threads, shm, st>>>(a, items, B, j, Kmax);
+    else
+      k_step_batched<T, S, LPL, false, 256><<<(unsigned)nwg, threads, 0, st>>>(a, items, B, j, Kmax);
+  }
+  check_launch("k_step_batched");
 }
 
 template <class T, int S>
@@ -244,6 +383,41 @@ void launch_step(hipStream_t st, int S, const StepArgs<T> &a, const StepShape &s
     default: throw Error(POLFED_EINVAL, "block width must be a power of two in [1, 64]");
   }
 }
+
+template <class T>
+void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const BatchItem<T> *items,
+                         int B, long long j, long long Kmax, const StepShape &shape, int num_cu) {
+  if (a.n <= 0 || B <= 0) return;
+  if (shape.threads != 256 && shape.threads != 1024)
+    throw Error(POLFED_EINVAL, "step kernel: threads must be 256 or 1024");
+#define PF_BATCH_CASE(SS)                                                              \
+  case SS:                                                                             \
+    if (shape.lpl == 2)                                                                \
+      launch_batched_s<T, SS, 2>(st, a, items, B, j, Kmax, shape, num_cu);             \
+    else if (shape.lpl == 4)                                                           \
+      launch_batched_s<T, SS, 4>(st, a, items, B, j, Kmax, shape, num_cu);             \
+    else                                                                               \
+      launch_batched_s<T, SS, 1>(st, a, items, B, j, Kmax, shape, num_cu);             \
+    break;
+  switch (S) {
+    PF_BATCH_CASE(1)
+    PF_BATCH_CASE(2)
+    PF_BATCH_CASE(4)
+    PF_BATCH_CASE(8)
+    PF_BATCH_CASE(16)
+    PF_BATCH_CASE(32)
+    PF_BATCH_CASE(64)
+    default: throw Error(POLFED_EINVAL, "block width must be a power of two in [1, 64]");
+  }
+#undef PF_BATCH_CASE
+}
+
+template void launch_step_batched<float>(hipStream_t, int, const StepArgs<float> &,
+                                         const BatchItem<float> *, int, long long, long long,
+                                         const StepShape &, int);
+template void launch_step_batched<double>(hipStream_t, int, const StepArgs<double> &,
+                                          const BatchItem<double> *, int, long long, long long,
+                                          const StepShape &, int);
 
 template void launch_step<float>(hipStream_t, int, const StepArgs<float> &, const StepShape &,
                                  int);

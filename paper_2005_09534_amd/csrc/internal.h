@@ -128,6 +128,24 @@ struct StepShape {
 
 template <class T>
 void launch_step(hipStream_t st, int S, const StepArgs<T> &a, const StepShape &shape, int num_cu);
+
+// One realisation of a batched filter (device-resident descriptor).
+template <class T>
+struct BatchItem {
+  const T *dt;         // a d + b
+  const T *X;          // n x S input block
+  T *buf;              // 3 n x S recurrence buffers
+  T *Y;                // n x S output
+  const double *coef;  // c_0 .. c_K (device)
+  double Dinv;         // 1 / D
+  T w1, w2;            // a J1, a J2
+  long long K;
+  int active;
+};
+
+template <class T>
+void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const BatchItem<T> *items,
+                         int B, long long j, long long Kmax, const StepShape &shape, int num_cu);
 // Built-in default shape (used when the context holds no tuned entry).
 StepShape default_shape(int L, int S, bool fp32);
 

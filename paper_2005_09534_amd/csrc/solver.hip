@@ -25,6 +25,8 @@
 #include <algorithm>
 #include <chrono>
 #include <iterator>
+#include <map>
+#include <memory>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -326,14 +328,6 @@ void run_bounds(polfed_ctx *ctx, const Chain &c, int steps, unsigned long long s
 
 // ------------------------------------------------------------- the solve --
 
-struct Lanczos {
-  long long n;
-  int s, P, m_max;
-  double *Q;  // n x P (ld P)
-  double *U, *U2;  // n x s
-  double *T;  // P x P
-};
-
 static int next_pow2_le(int x) {
   int s = 1;
   while (s * 2 <= x) s *= 2;
@@ -342,274 +336,314 @@ static int next_pow2_le(int x) {
 
 int choose_block(int L, int nev, int precision);
 
-template <class T>
-static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int nev,
-                      double *evals, double *evecs, double *resid, polfed_info *info);
-
-int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opts_in, int nev,
-              double *evals, double *evecs, double *resid, polfed_info *info) {
+static polfed_opts resolve_opts(const polfed_opts *in) {
   polfed_opts o;
   polfed_default_opts(&o);
-  if (opts_in) o = *opts_in;
+  if (in) o = *in;
   if (o.p <= 0.0) o.p = 0.17;
   if (o.window_factor <= 0.0) o.window_factor = 1.5;
   if (o.tol <= 0.0) o.tol = 1e-10;
   if (o.eta <= 0.0) o.eta = 1e-3;
   if (o.bounds_steps <= 0) o.bounds_steps = 200;
   PF_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
-  PF_REQUIRE(evals != nullptr && resid != nullptr, "evals and resid must not be NULL");
-  Chain c;
-  make_chain(ctx, model, c);
-  const long long n = c.basis->n;
-  PF_REQUIRE(nev >= 1 && nev <= n, "nev must be in [1, dim]");
   PF_REQUIRE(o.target_kind == 0 || o.target_kind == 1, "target_kind must be 0 or 1");
   if (o.target_kind == 0) PF_REQUIRE(o.target > 0.0 && o.target < 1.0, "eps target must be in (0,1)");
+  return o;
+}
+
+// The state of one POLFED solve (one realisation): setup, then alternately
+// filter_X() / [the filter, alone or batched] / lanczos_step() until done,
+// then finalize().  Device state that must live across Lanczos steps is
+// owned here; scratch that is consumed within one step is the context's.
+template <class T>
+struct Realization {
+  polfed_ctx *ctx = nullptr;
+  Chain c;
+  polfed_opts o;
+  int nev = 0;
+  bool fp32 = sizeof(T) == 4;
+  long long n = 0;
+  int s = 0, P = 0, m_max = 0, nwin = 0;
+  double E0 = 0, E1 = 0, r0 = 0, r1 = 0, E0w = 0, E1w = 0, a = 0, b = 0;
+  double sigma_H = 0, sigma = 0, normH = 0, tau = 0;
+  long long K = 0;
+  std::vector<double> coef;
+  double D = 1.0;
+  DevBuf Qb, Tmb, dtb, Xb, Yb, Bb, coefb, chebb;
+  int m_done = 0, nconv = 0, refills = 0;
+  bool done = false;
+  double t_start = 0, t_bounds = 0, t_filter = 0, t_orth = 0, t_eig = 0, bytes = 0;
+  double filter_gpu_s = 0, filter_launches = 0;
+
+  double *Q() const { return Qb.as<double>(); }
+  double *Tm() const { return Tmb.as<double>(); }
+  T *dt() const { return dtb.as<T>(); }
+  T *Xs() const { return Xb.as<T>(); }
+  T *Ys() const { return Yb.as<T>(); }
+  double *Bcur() const { return Bb.as<double>(); }
+  double *BT() const { return Bb.as<double>() + (size_t)s * s; }
+
+  void setup(polfed_ctx *ctx_, const polfed_model *model, const polfed_opts &o_, int nev_);
+  const T *filter_X();
+  void lanczos_step();
+  int finalize(double *evals, double *evecs, double *resid, polfed_info *info);
+
+ private:
+  int cholqr2(double *X, double *out, long long ldo);
+  void refill_block(const double *Uorig, double *out, long long ldo, int pc, int j);
+};
+
+template <class T>
+void Realization<T>::setup(polfed_ctx *ctx_, const polfed_model *model, const polfed_opts &o_,
+                           int nev_) {
+  ctx = ctx_;
+  o = o_;
+  nev = nev_;
+  hipStream_t st = ctx->stream;
+  t_start = now_s();
+  make_chain(ctx, model, c);
+  n = c.basis->n;
+  PF_REQUIRE(nev >= 1 && nev <= n, "nev must be in [1, dim]");
   if (o.block_size == 0) o.block_size = choose_block(c.L, nev, o.precision);
   PF_REQUIRE(o.block_size >= 1 && o.block_size <= 64 &&
                  (o.block_size & (o.block_size - 1)) == 0,
              "block_size must be a power of two in [1, 64]");
-  if (o.precision == 1)
-    return solve_impl<float>(ctx, c, o, nev, evals, evecs, resid, info);
-  return solve_impl<double>(ctx, c, o, nev, evals, evecs, resid, info);
-}
+  s = o.block_size;
 
-template <class T>
-static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int nev,
-                      double *evals, double *evecs, double *resid, polfed_info *info) {
-  const bool fp32 = sizeof(T) == 4;
-  hipStream_t st = ctx->stream;
-  const long long n = c.basis->n;
-  polfed_info inf;
-  std::memset(&inf, 0, sizeof(inf));
-  const double t_start = now_s();
-  ctx->filter_gpu_s = 0.0;
-  ctx->filter_launches = 0.0;
-  ctx->filter_bytes = 0.0;
-
-  // 1-2: bounds and rescale
-  double E0, E1, r0, r1;
+  // spectral bounds, widened by the residual bounds and eta (E1 - E0)
   run_bounds(ctx, c, o.bounds_steps, o.seed ^ 0xb0b0ull, E0, E1, r0, r1);
   const double width = E1 - E0;
   PF_REQUIRE(width > 0.0, "spectrum has zero width");
-  const double E0w = E0 - r0 - o.eta * width, E1w = E1 + r1 + o.eta * width;
-  const double a = 2.0 / (E1w - E0w), b = -(E0w + E1w) / (E1w - E0w);
-  const double sigma_H = (o.target_kind == 0) ? E0 + o.target * width : o.target;
-  const double sigma = a * sigma_H + b;
+  E0w = E0 - r0 - o.eta * width;
+  E1w = E1 + r1 + o.eta * width;
+  a = 2.0 / (E1w - E0w);
+  b = -(E0w + E1w) / (E1w - E0w);
+  sigma_H = (o.target_kind == 0) ? E0 + o.target * width : o.target;
+  sigma = a * sigma_H + b;
   PF_REQUIRE(std::fabs(sigma) < 1.0, "target lies outside the spectral bounds");
-  const double normH = std::max(std::fabs(E0), std::fabs(E1));
-  inf.t_bounds = now_s() - t_start;
+  normH = std::max(std::fabs(E0), std::fabs(E1));
+  t_bounds = now_s() - t_start;
 
-  // 3: order
-  const int s = o.block_size;
-  int nwin = (int)std::ceil(o.window_factor * nev);
-  nwin = (int)std::min<long long>(nwin, n);
-  long long K = o.K;
-  double rho = 0.0;
+  // order from the density of states for a window of N_win eigenvalues
+  nwin = (int)std::min<long long>((long long)std::ceil(o.window_factor * nev), n);
+  K = o.K;
   if (K <= 0) {
+    double rho = 0.0;
     const double Gamma = dos_gamma(c.L, c.J1, c.J2, c.Delta, c.h);
     const double Ebar = trace_mean(c.L, c.J1, c.J2, c.Delta);
     K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, &rho);
   }
-  std::vector<double> coef;
-  double D;
   cheb_coeffs(sigma, K, coef, D);
-
-  // column cap: 4 N_win + 6 s in whole blocks, at most n
-  long long cols = (o.max_cols > 0) ? o.max_cols : 4LL * nwin + 6LL * s;
+  // column cap: 6 N_win + 6 s in whole blocks, at most n
+  long long cols = (o.max_cols > 0) ? o.max_cols : 6LL * nwin + 6LL * s;
   cols = std::min<long long>(cols, (n / s) * s);
-  int m_max = (int)std::max<long long>(1, cols / s);
-  const int P = m_max * s;
+  m_max = (int)std::max<long long>(1, cols / s);
+  P = m_max * s;
+  // convergence threshold on ||B t~||: FP64 filter 1e-10; FP32 filter its
+  // rounding floor ~eps32 sqrt(K)
+  tau = fp32 ? std::max(1e-10, 30.0 * 1.1920929e-7 * std::sqrt((double)K)) : 1e-10;
 
-  // tau for ||B t~||: FP64 filter 1e-10; FP32 filter its noise floor
-  const double tau = fp32 ? std::max(1e-10, 30.0 * 1.1920929e-7 * std::sqrt((double)K)) : 1e-10;
+  Qb.ensure(sizeof(double) * (size_t)n * P);
+  Tmb.ensure(sizeof(double) * (size_t)P * P);
+  dtb.ensure(sizeof(T) * n);
+  Xb.ensure(sizeof(T) * (size_t)n * s);
+  Yb.ensure(sizeof(T) * (size_t)n * s);
+  Bb.ensure(sizeof(double) * 2 * (size_t)s * s);
+  launch_scaled_diag<T>(st, n, c.diag.as<double>(), a, b, dt());
+  launch_fill(st, Tm(), (long long)P * P, 0.0);
 
-  // 4: buffers
-  double *Q = static_cast<double *>(ctx->buf("Q").ensure(sizeof(double) * (size_t)n * P));
+  // start block Q_1: Philox entries, orthonormalised
+  double *U = static_cast<double *>(ctx->buf("U").ensure(sizeof(double) * (size_t)n * s));
+  launch_philox_fill(st, n, s, U, s, o.seed, 1u);
+  if (cholqr2(U, Q(), P) != 0) throw Error(POLFED_EBREAKDOWN, "start block is rank deficient");
+}
+
+// CholeskyQR2 of X (n x s, ld s) into out (ld ldo); Bcur = its R factor.
+// Returns the flag of the first pivot below 1e-14 of the largest diagonal
+// of the Gram matrix (0 = fine): beyond a condition number of ~1e7
+// CholeskyQR2 no longer restores orthogonality, and the refill path takes
+// over.
+template <class T>
+int Realization<T>::cholqr2(double *X, double *out, long long ldo) {
+  hipStream_t st = ctx->stream;
+  DevBuf &partials = ctx->buf("partials");
+  double *sm = static_cast<double *>(ctx->buf("cqr").ensure(sizeof(double) * 5 * 64 * 64));
+  double *G = sm, *Rinv1 = sm + 4096, *B1 = sm + 2 * 4096, *Rinv2 = sm + 3 * 4096, *B2 = sm + 4 * 4096;
+  double *U2 = static_cast<double *>(ctx->buf("U2").ensure(sizeof(double) * (size_t)n * s));
+  int *flag = static_cast<int *>(ctx->buf("flag").ensure(64));
+  launch_gram(st, n, s, s, X, s, X, s, G, s, partials, ctx->num_cu);
+  launch_chol(st, s, G, Rinv1, B1, flag, 1e-14);
+  launch_update(st, n, s, s, 1.0, X, s, Rinv1, s, 0.0, U2, s);
+  launch_gram(st, n, s, s, U2, s, U2, s, G, s, partials, ctx->num_cu);
+  launch_chol(st, s, G, Rinv2, B2, flag + 1, 1e-14);
+  launch_update(st, n, s, s, 1.0, U2, s, Rinv2, s, 0.0, out, ldo);
+  launch_small_gemm(st, s, s, s, B2, s, B1, s, Bcur(), s, 0);
+  int hf[2] = {0, 0};
+  PF_HIP(hipMemcpyAsync(hf, flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
+  return hf[0] ? hf[0] : hf[1];
+}
+
+// The block lost rank (the Krylov space is nearly exhausted, which happens
+// when n is small).  Keep the well-conditioned directions of U and refill
+// the rest with random vectors orthogonal to Qm; then B_{j+1} = Q_{j+1}^T U,
+// so that U = Q_{j+1} B_{j+1} still holds on the kept directions (B is no
+// longer triangular; T_m does not need it to be).
+template <class T>
+void Realization<T>::refill_block(const double *Uorig, double *out, long long ldo, int pc, int j) {
+  hipStream_t st = ctx->stream;
+  DevBuf &partials = ctx->buf("partials");
+  ++refills;
+  double *Wg = static_cast<double *>(ctx->buf("Wg").ensure(sizeof(double) * ((size_t)s * s * 4 + 2 * s)));
+  double *G = Wg + (size_t)3 * s * s;
   double *U = static_cast<double *>(ctx->buf("U").ensure(sizeof(double) * (size_t)n * s));
   double *U2 = static_cast<double *>(ctx->buf("U2").ensure(sizeof(double) * (size_t)n * s));
-  double *Tm = static_cast<double *>(ctx->buf("T").ensure(sizeof(double) * (size_t)P * P));
-  double *small = static_cast<double *>(ctx->buf("small").ensure(sizeof(double) * (8 * 64 * 64 + (size_t)P * 64)));
-  double *Ablk = small, *G = small + 4096, *Rinv1 = small + 2 * 4096, *B1 = small + 3 * 4096;
-  double *Rinv2 = small + 4 * 4096, *B2 = small + 5 * 4096, *Bcur = small + 6 * 4096,
-         *BT = small + 7 * 4096, *Cproj = small + 8 * 4096;
-  int *flag = static_cast<int *>(ctx->buf("flag").ensure(64));
-  T *bufs = static_cast<T *>(ctx->buf("cheb").ensure(sizeof(T) * 3 * (size_t)n * s));
-  T *dt = static_cast<T *>(ctx->buf("dt").ensure(sizeof(T) * n));
-  T *Xf = nullptr, *Yf = nullptr;
-  if (fp32) {
-    Xf = static_cast<T *>(ctx->buf("Xf").ensure(sizeof(T) * (size_t)n * s));
-    Yf = static_cast<T *>(ctx->buf("Yf").ensure(sizeof(T) * (size_t)n * s));
+  double *Cproj = static_cast<double *>(ctx->buf("Cproj").ensure(sizeof(double) * (size_t)P * s));
+  launch_gram(st, n, s, s, Uorig, s, Uorig, s, G, s, partials, ctx->num_cu);
+  launch_symmetrize(st, s, G, s);
+  double *lam = Wg + (size_t)2 * s * s, *W = Wg;
+  sym_eig(st, s, G, lam, W, ctx->buf("eigwork_small"));
+  std::vector<double> hl(s), hW((size_t)s * s);
+  PF_HIP(hipMemcpyAsync(hl.data(), lam, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipMemcpyAsync(hW.data(), W, sizeof(double) * s * s, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
+  const double lmax = std::max(hl[s - 1], 0.0);
+  // kept directions: U w_i / sqrt(lambda_i) for lambda_i > 1e-20 lambda_max
+  std::vector<double> M((size_t)s * s, 0.0);
+  int r = 0;
+  for (int i = s - 1; i >= 0; --i) {
+    if (!(hl[i] > 1e-20 * lmax) || lmax == 0.0) continue;
+    for (int k = 0; k < s; ++k) M[(size_t)k * s + r] = hW[(size_t)k * s + i] / std::sqrt(hl[i]);
+    ++r;
   }
+  double *Md = Wg + (size_t)s * s;
+  PF_HIP(hipMemcpyAsync(Md, M.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
+  launch_update(st, n, s, s, 1.0, Uorig, s, Md, s, 0.0, U2, s);  // columns >= r are zero
+  if ((long long)pc + s > n) {
+    // no room for s new directions (only at the last block of a tiny
+    // problem, where only B_{j+1} is used): keep the r directions
+    launch_cast<double, double>(st, n, s, U2, s, out, ldo);
+    launch_gram(st, n, s, s, out, ldo, Uorig, s, Bcur(), s, partials, ctx->num_cu);
+    return;
+  }
+  // random columns r..s-1, then the whole block against Qm (twice) and QR
+  launch_philox_fill(st, n, s - r, U2 + r, s, o.seed + 977ull * (j + 1) + 13ull * refills, 2u);
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_gram(st, n, pc, s, Q(), P, U2, s, Cproj, s, partials, ctx->num_cu);
+    launch_update(st, n, pc, s, -1.0, Q(), P, Cproj, s, 1.0, U2, s);
+  }
+  PF_HIP(hipMemcpyAsync(U, U2, sizeof(double) * n * s, hipMemcpyDeviceToDevice, st));
+  if (cholqr2(U, out, ldo) != 0)
+    throw Error(POLFED_EBREAKDOWN, "Lanczos block lost rank and could not be refilled");
+  launch_gram(st, n, s, s, out, ldo, Uorig, s, Bcur(), s, partials, ctx->num_cu);
+}
+
+// Stage Q_j (j = m_done) as the filter input in T (a fixed buffer, so that a
+// captured filter graph stays valid from block to block).
+template <class T>
+const T *Realization<T>::filter_X() {
+  launch_cast<double, T>(ctx->stream, n, s, Q() + (size_t)m_done * s, P, Xs(), s);
+  return Xs();
+}
+
+// One block-Lanczos step on the filtered block Y = P(H~) Q_j (in Ys()):
+// eqs. (Lan1)-(Lan2) with full reorthogonalisation, T_m, and the
+// convergence test on the eigenpairs of T_m.
+template <class T>
+void Realization<T>::lanczos_step() {
+  hipStream_t st = ctx->stream;
   DevBuf &partials = ctx->buf("partials");
-  launch_scaled_diag<T>(st, n, c.diag.as<double>(), a, b, dt);
-  launch_fill(st, Tm, (long long)P * P, 0.0);
-
-  // CholeskyQR2 of X (n x s, ld s) into out (ld ldo); B = R factor.
-  // Returns the flag of the first pivot below 1e-14 of the largest diagonal
-  // of the Gram matrix (0 = fine): beyond a condition number of ~1e7
-  // CholeskyQR2 no longer restores orthogonality, and the refill path takes
-  // over.
-  std::vector<int> hf(2);
-  auto cholqr2 = [&](double *X, double *out, long long ldo) -> int {
-    launch_gram(st, n, s, s, X, s, X, s, G, s, partials, ctx->num_cu);
-    launch_chol(st, s, G, Rinv1, B1, flag, 1e-14);
-    launch_update(st, n, s, s, 1.0, X, s, Rinv1, s, 0.0, U2, s);
-    launch_gram(st, n, s, s, U2, s, U2, s, G, s, partials, ctx->num_cu);
-    launch_chol(st, s, G, Rinv2, B2, flag + 1, 1e-14);
-    launch_update(st, n, s, s, 1.0, U2, s, Rinv2, s, 0.0, out, ldo);
-    launch_small_gemm(st, s, s, s, B2, s, B1, s, Bcur, s, 0);
-    PF_HIP(hipMemcpyAsync(hf.data(), flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    PF_HIP(hipStreamSynchronize(st));
-    return hf[0] ? hf[0] : hf[1];
-  };
-
+  const int j = m_done;
+  double t1 = now_s();
+  double *U = static_cast<double *>(ctx->buf("U").ensure(sizeof(double) * (size_t)n * s));
   double *Usave = static_cast<double *>(ctx->buf("Usave").ensure(sizeof(double) * (size_t)n * s));
-  double *Wg = static_cast<double *>(ctx->buf("Wg").ensure(sizeof(double) * (size_t)s * s * 3 + 2 * s));
-  DevBuf &eigw = ctx->buf("eigwork_small");
-  int refills = 0;
-  auto refill_block = [&](const double *Uorig, double *out, long long ldo, int pc, int j) {
-    ++refills;
-    // eigen-decomposition of G = U^T U
-    launch_gram(st, n, s, s, Uorig, s, Uorig, s, G, s, partials, ctx->num_cu);
-    launch_symmetrize(st, s, G, s);
-    double *lam = Wg + (size_t)2 * s * s, *W = Wg;
-    sym_eig(st, s, G, lam, W, eigw);
-    std::vector<double> hl(s), hW((size_t)s * s);
-    PF_HIP(hipMemcpyAsync(hl.data(), lam, sizeof(double) * s, hipMemcpyDeviceToHost, st));
-    PF_HIP(hipMemcpyAsync(hW.data(), W, sizeof(double) * s * s, hipMemcpyDeviceToHost, st));
+  double *Cproj = static_cast<double *>(ctx->buf("Cproj").ensure(sizeof(double) * (size_t)P * s));
+  double *Ablk = static_cast<double *>(ctx->buf("Ablk").ensure(sizeof(double) * 64 * 64));
+  launch_cast<T, double>(st, n, s, Ys(), s, U, s);
+  double *Qj = Q() + (size_t)j * s;
+  // Lan1: U -= Q_{j-1} B_j^T ; A_j = sym(Q_j^T U) ; U -= Q_j A_j
+  if (j > 0) launch_update(st, n, s, s, -1.0, Q() + (size_t)(j - 1) * s, P, BT(), s, 1.0, U, s);
+  launch_gram(st, n, s, s, Qj, P, U, s, Ablk, s, partials, ctx->num_cu);
+  launch_symmetrize(st, s, Ablk, s);
+  launch_update(st, n, s, s, -1.0, Qj, P, Ablk, s, 1.0, U, s);
+  PF_HIP(hipMemcpy2DAsync(Tm() + (size_t)j * s * P + j * s, sizeof(double) * P, Ablk,
+                          sizeof(double) * s, sizeof(double) * s, s, hipMemcpyDeviceToDevice, st));
+  // full reorthogonalisation against Q_1..Q_j, twice
+  const int pc = (j + 1) * s;
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_gram(st, n, pc, s, Q(), P, U, s, Cproj, s, partials, ctx->num_cu);
+    launch_update(st, n, pc, s, -1.0, Q(), P, Cproj, s, 1.0, U, s);
+  }
+  // Lan2: Q_{j+1} B_{j+1} = U  (after the last block Q_{j+1} lands in U:
+  // only B_{j+1} is needed)
+  double *Qnext = (j + 1 < m_max) ? Q() + (size_t)(j + 1) * s : U;
+  const long long ldq = (j + 1 < m_max) ? P : s;
+  PF_HIP(hipMemcpyAsync(Usave, U, sizeof(double) * n * s, hipMemcpyDeviceToDevice, st));
+  if (cholqr2(U, Qnext, ldq) != 0) refill_block(Usave, Qnext, ldq, pc, j);
+  launch_small_transpose(st, s, s, Bcur(), s, BT(), s);
+  if (j + 1 < m_max) {
+    PF_HIP(hipMemcpy2DAsync(Tm() + (size_t)(j + 1) * s * P + j * s, sizeof(double) * P, Bcur(),
+                            sizeof(double) * s, sizeof(double) * s, s, hipMemcpyDeviceToDevice, st));
+    PF_HIP(hipMemcpy2DAsync(Tm() + (size_t)j * s * P + (j + 1) * s, sizeof(double) * P, BT(),
+                            sizeof(double) * s, sizeof(double) * s, s, hipMemcpyDeviceToDevice, st));
+  }
+  double t2 = now_s();
+  t_orth += t2 - t1;
+  m_done = j + 1;
+  const int ms = m_done * s;
+  const int check_from = std::max(s, std::min(nev, P));
+  if (ms >= check_from || m_done == m_max) {
+    // eigenpairs of T_m; residual_i = ||B_{j+1} t~_i||, t~_i the last s
+    // components of t_i
+    double *Tw = static_cast<double *>(ctx->buf("Tw").ensure(sizeof(double) * (size_t)P * P));
+    double *Vt = static_cast<double *>(ctx->buf("Vt").ensure(sizeof(double) * (size_t)P * P));
+    double *th = static_cast<double *>(ctx->buf("theta").ensure(sizeof(double) * (size_t)P * 2));
+    double *Rres = static_cast<double *>(ctx->buf("Rres").ensure(sizeof(double) * (size_t)64 * P));
+    PF_HIP(hipMemcpy2DAsync(Tw, sizeof(double) * ms, Tm(), sizeof(double) * P, sizeof(double) * ms,
+                            ms, hipMemcpyDeviceToDevice, st));
+    sym_eig(st, ms, Tw, th, Vt, ctx->buf("eigwork"));
+    launch_small_gemm(st, s, s, ms, Bcur(), s, Vt + (size_t)(ms - s) * ms, ms, Rres, ms, 0);
+    launch_colnorms(st, s, ms, Rres, ms, th + ms, partials, ctx->num_cu);
+    std::vector<double> theta(ms), tres(ms);
+    PF_HIP(hipMemcpyAsync(theta.data(), th, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipMemcpyAsync(tres.data(), th + ms, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
     PF_HIP(hipStreamSynchronize(st));
-    const double lmax = std::max(hl[s - 1], 0.0);
-    // kept directions: U w_i / sqrt(lambda_i) for lambda_i > 1e-20 lambda_max
-    std::vector<double> M((size_t)s * s, 0.0);
-    int r = 0;
-    for (int i = s - 1; i >= 0; --i) {
-      if (!(hl[i] > 1e-20 * lmax) || lmax == 0.0) continue;
-      for (int k = 0; k < s; ++k) M[(size_t)k * s + r] = hW[(size_t)k * s + i] / std::sqrt(hl[i]);
-      ++r;
-    }
-    double *Md = Wg + (size_t)s * s;
-    PF_HIP(hipMemcpyAsync(Md, M.data(), sizeof(double) * s * s, hipMemcpyHostToDevice, st));
-    launch_update(st, n, s, s, 1.0, Uorig, s, Md, s, 0.0, U2, s);  // columns >= r are zero
-    if ((long long)pc + s > n) {
-      // no room for s new directions (only at the last block of a tiny
-      // problem, where only B_{j+1} is used): keep the r directions, leave
-      // the rest zero
-      launch_cast<double, double>(st, n, s, U2, s, out, ldo);
-      launch_gram(st, n, s, s, out, ldo, Uorig, s, Bcur, s, partials, ctx->num_cu);
-      return;
-    }
-    // random columns r..s-1, then the whole block against Qm (twice) and QR
-    launch_philox_fill(st, n, s - r, U2 + r, s, o.seed + 977ull * (j + 1) + 13ull * refills, 2u);
-    for (int pass = 0; pass < 2; ++pass) {
-      launch_gram(st, n, pc, s, Q, P, U2, s, Cproj, s, partials, ctx->num_cu);
-      launch_update(st, n, pc, s, -1.0, Q, P, Cproj, s, 1.0, U2, s);
-    }
-    PF_HIP(hipMemcpyAsync(U, U2, sizeof(double) * n * s, hipMemcpyDeviceToDevice, st));
-    if (cholqr2(U, out, ldo) != 0)
-      throw Error(POLFED_EBREAKDOWN, "Lanczos block lost rank and could not be refilled");
-    // B_{j+1} = Q_{j+1}^T U_orig
-    launch_gram(st, n, s, s, out, ldo, Uorig, s, Bcur, s, partials, ctx->num_cu);
-  };
+    // converged: theta_i >= p and ||B t~_i|| <= tau; when fewer than nev
+    // Ritz values exceed p (the Gaussian DOS overestimated the window), the
+    // nev largest theta take their place
+    double thr = o.p;
+    int above = 0;
+    for (int i = 0; i < ms; ++i) above += theta[i] >= o.p;
+    if (above < nev) thr = theta[std::max(0, ms - nev)];  // ascending order
+    nconv = 0;
+    for (int i = 0; i < ms; ++i)
+      if (theta[i] >= thr && tres[i] <= tau) ++nconv;
+    t_eig += now_s() - t2;
+  }
+  if (nconv >= nev || m_done >= m_max) done = true;
+}
 
-  // start block
-  launch_philox_fill(st, n, s, U, s, o.seed, 1u);
-  if (cholqr2(U, Q, P) != 0) throw Error(POLFED_EBREAKDOWN, "start block is rank deficient");
-
-  double t_filter = 0, t_orth = 0, t_eig = 0;
-  double bytes = 0.0;
-  int m_done = 0, nconv = 0;
-  std::vector<double> theta, tres;
+template <class T>
+int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed_info *info) {
+  hipStream_t st = ctx->stream;
+  DevBuf &partials = ctx->buf("partials");
+  DevBuf &eigwork = ctx->buf("eigwork");
+  const int ms = m_done * s;
+  const bool converged = nconv >= nev;
+  polfed_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.t_bounds = t_bounds;
+  double *Qp = Q();
+  // the eigenpairs of the final T_m
   double *Tw = static_cast<double *>(ctx->buf("Tw").ensure(sizeof(double) * (size_t)P * P));
   double *Vt = static_cast<double *>(ctx->buf("Vt").ensure(sizeof(double) * (size_t)P * P));
   double *th = static_cast<double *>(ctx->buf("theta").ensure(sizeof(double) * (size_t)P * 2));
-  double *Rres = static_cast<double *>(ctx->buf("Rres").ensure(sizeof(double) * (size_t)64 * P));
-  DevBuf &eigwork = ctx->buf("eigwork");
-  const int check_from = std::max(s, std::min(nev, P));  // columns before the first T_m check
-
-  for (int j = 0; j < m_max; ++j) {
-    double t0 = now_s();
-    double *Qj = Q + (size_t)j * s;
-    // U = P(H~) Q_j
-    if (fp32) {
-      launch_cast<double, float>(st, n, s, Qj, P, reinterpret_cast<float *>(Xf), s);
-      run_filter<T>(ctx, c, dt, a, s, Xf, s, Yf, s, K, coef, D, bufs, true, &bytes);
-      launch_cast<float, double>(st, n, s, reinterpret_cast<float *>(Yf), s, U, s);
-    } else {
-      // stage Q_j in a fixed buffer so that the filter's graph is the same
-      // for every block
-      double *Xs = static_cast<double *>(ctx->buf("Xs").ensure(sizeof(double) * (size_t)n * s));
-      launch_cast<double, double>(st, n, s, Qj, P, Xs, s);
-      run_filter<T>(ctx, c, dt, a, s, reinterpret_cast<T *>(Xs), s, reinterpret_cast<T *>(U), s,
-                    K, coef, D, bufs, false, &bytes);
-    }
-    PF_HIP(hipStreamSynchronize(st));
-    double t1 = now_s();
-    t_filter += t1 - t0;
-    // Lan1: U -= Q_{j-1} B_j^T ; A_j = sym(Q_j^T U) ; U -= Q_j A_j
-    if (j > 0) launch_update(st, n, s, s, -1.0, Q + (size_t)(j - 1) * s, P, BT, s, 1.0, U, s);
-    launch_gram(st, n, s, s, Qj, P, U, s, Ablk, s, partials, ctx->num_cu);
-    launch_symmetrize(st, s, Ablk, s);
-    launch_update(st, n, s, s, -1.0, Qj, P, Ablk, s, 1.0, U, s);
-    PF_HIP(hipMemcpy2DAsync(Tm + (size_t)j * s * P + j * s, sizeof(double) * P, Ablk,
-                            sizeof(double) * s, sizeof(double) * s, s, hipMemcpyDeviceToDevice,
-                            st));
-    // full reorthogonalisation against Q_1..Q_j, twice
-    const int pc = (j + 1) * s;
-    for (int pass = 0; pass < 2; ++pass) {
-      launch_gram(st, n, pc, s, Q, P, U, s, Cproj, s, partials, ctx->num_cu);
-      launch_update(st, n, pc, s, -1.0, Q, P, Cproj, s, 1.0, U, s);
-    }
-    // Lan2: Q_{j+1} B_{j+1} = U
-    // (no slot left after the last block: Q_{j+1} lands in U, only B_{j+1}
-    // is needed)
-    double *Qnext = (j + 1 < m_max) ? Q + (size_t)(j + 1) * s : U;
-    long long ldq = (j + 1 < m_max) ? P : s;
-    PF_HIP(hipMemcpyAsync(Usave, U, sizeof(double) * n * s, hipMemcpyDeviceToDevice, st));
-    int bad = cholqr2(U, Qnext, ldq);
-    if (bad != 0) {
-      // The block lost rank (the Krylov space is nearly exhausted, which
-      // happens when n is small).  Keep the well-conditioned directions of U
-      // and refill the rest with random vectors orthogonal to Qm; then
-      // B_{j+1} = Q_{j+1}^T U, so that U = Q_{j+1} B_{j+1} still holds on the
-      // kept directions (B is no longer triangular; T_m does not need it).
-      refill_block(Usave, Qnext, ldq, pc, j);
-    }
-    launch_small_transpose(st, s, s, Bcur, s, BT, s);
-    if (j + 1 < m_max) {
-      PF_HIP(hipMemcpy2DAsync(Tm + (size_t)(j + 1) * s * P + j * s, sizeof(double) * P, Bcur,
-                              sizeof(double) * s, sizeof(double) * s, s,
-                              hipMemcpyDeviceToDevice, st));
-      PF_HIP(hipMemcpy2DAsync(Tm + (size_t)j * s * P + (j + 1) * s, sizeof(double) * P, BT,
-                              sizeof(double) * s, sizeof(double) * s, s,
-                              hipMemcpyDeviceToDevice, st));
-    }
-    double t2 = now_s();
-    t_orth += t2 - t1;
-    m_done = j + 1;
-    const int ms = m_done * s;
-    // eigenpairs of T_m and the convergence test
-    if (ms >= check_from || j + 1 == m_max) {
-      PF_HIP(hipMemcpy2DAsync(Tw, sizeof(double) * ms, Tm, sizeof(double) * P,
-                              sizeof(double) * ms, ms, hipMemcpyDeviceToDevice, st));
-      sym_eig(st, ms, Tw, th, Vt, eigwork);
-      // R = B_{j+1} * V[ms-s:ms, :]  (s x ms), residual_i = ||R[:, i]||
-      launch_small_gemm(st, s, s, ms, Bcur, s, Vt + (size_t)(ms - s) * ms, ms, Rres, ms, 0);
-      launch_colnorms(st, s, ms, Rres, ms, th + ms, partials, ctx->num_cu);
-      theta.resize(ms);
-      tres.resize(ms);
-      PF_HIP(hipMemcpyAsync(theta.data(), th, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
-      PF_HIP(hipMemcpyAsync(tres.data(), th + ms, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
-      PF_HIP(hipStreamSynchronize(st));
-      nconv = 0;
-      for (int i = 0; i < ms; ++i)
-        if (theta[i] >= o.p && tres[i] <= tau) ++nconv;
-      t_eig += now_s() - t2;
-      if (nconv >= nev) break;
-    }
-  }
-  const int ms = m_done * s;
-  const bool converged = nconv >= nev;
-
+  PF_HIP(hipMemcpy2DAsync(Tw, sizeof(double) * ms, Tm(), sizeof(double) * P, sizeof(double) * ms, ms,
+                          hipMemcpyDeviceToDevice, st));
+  sym_eig(st, ms, Tw, th, Vt, eigwork);
+  std::vector<double> theta(ms);
+  PF_HIP(hipMemcpyAsync(theta.data(), th, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
   // 7: Rayleigh-Ritz of H~, selection of the nev nearest the target, and
   // residuals with the unscaled H
   double t3 = now_s();
@@ -624,6 +658,7 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
   int *didx = static_cast<int *>(ctx->buf("idx").ensure(sizeof(int) * (size_t)(P + 64) * 2));
   std::vector<double> Esel, r;
   double refine_bytes = 0.0, t_refine = 0.0, rr_apps = 0.0;
+  const double ctx_gpu0 = ctx->filter_gpu_s, ctx_launch0 = ctx->filter_launches;
   int passes = 0, nout = 0;
   const bool verbose = std::getenv("POLFED_VERBOSE") != nullptr;
 
@@ -678,16 +713,20 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
     std::vector<int> cand;
     for (int i = 0; i < ms; ++i)
       if (theta[i] >= o.p) cand.push_back(i);
-    if ((int)cand.size() < nev) {
+    const int above = (int)cand.size();
+    // at least nev candidates (the nev largest theta when fewer pass p)
+    const int want = nev;
+    if ((int)cand.size() < want) {
       cand.clear();
-      for (int i = ms - 1; i >= 0 && (int)cand.size() < nev; --i) cand.push_back(i);
+      for (int i = ms - 1; i >= 0 && (int)cand.size() < want; --i) cand.push_back(i);
       std::sort(cand.begin(), cand.end());
     }
     const int nc = (int)cand.size();
-    // refined columns (FP32 mode): the nev + margin nearest, padded to whole
+    // refined columns (FP32 mode): all candidates, so that every in-window
+    // error direction lies in the Rayleigh-Ritz space; padded to whole
     // kernel widths (a power of two up to 64, then multiples of 64) so that a
     // short, launch-bound step moves as many columns as possible
-    const int q = std::min(nc, nev + std::max(8, nev / 4));
+    const int q = nc;
     int qpad = 1;
     while (qpad < q && qpad < 64) qpad *= 2;
     if (q > 64) qpad = ((q + 63) / 64) * 64;
@@ -699,7 +738,7 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
     double *WR = static_cast<double *>(ctx->buf("WR").ensure(sizeof(double) * (size_t)n * ldr));
     for (int c0 = 0; c0 < nc; c0 += 64) {
       const int w = std::min(64, nc - c0);
-      launch_update(st, n, ms, w, 1.0, Q, P, Tsel + c0, ldr, 0.0, UR + c0, ldr);
+      launch_update(st, n, ms, w, 1.0, Qp, P, Tsel + c0, ldr, 0.0, UR + c0, ldr);
     }
     double *Gr = static_cast<double *>(ctx->buf("Gr").ensure(sizeof(double) * (size_t)ldr * ldr * 3 + 16));
     double *Yr = Gr + (size_t)ldr * ldr;
@@ -734,20 +773,22 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
     // FP64 refinement of the FP32-filter mode.  The FP32 rounding of the
     // recurrence leaves errors ~eps32 sqrt(K) in the Ritz vectors, largest
     // along eigenvectors whose theta is close to theta_i.  Subspace iteration
-    // with the FP64 filter P^{K_r}(H~) on the nearest q Ritz vectors damps a
-    // component at angular distance u from the target by ~1/(K_r u) relative
-    // to the wanted ones (near-window components by theta_k / theta_i), and
-    // Rayleigh-Ritz on the filtered span removes the mixing; K_r = K/4, K/2,
-    // K, K.  Target: 2e-9 ||H|| (or tol if looser), 5x under the 1e-8 ||H||
-    // bar for returned residuals.
+    // with the FP64 filter P^{K_r}(H~) on the q candidate Ritz vectors damps
+    // a component at angular distance u from the target by ~1/(K_r u)
+    // relative to the wanted ones (near-window components by theta_k /
+    // theta_i), and Rayleigh-Ritz on the filtered span removes the mixing;
+    // K_r = K/4, K/2, then K, at most 8 passes.  Target: 2e-9 ||H|| (or tol
+    // if looser), 5x under the 1e-8 ||H|| bar for returned residuals.
     const double target = std::max(o.tol, 2e-9) * normH;
-    long long K_r = std::max<long long>(16, K / 4);
+    const long long K_ref = K;
+    long long K_r = std::max<long long>(16, K_ref / 4);
+    (void)above;
     std::vector<double> coef_r;
     double D_r = 1.0;
     double *Vn = static_cast<double *>(ctx->buf("Vn").ensure(sizeof(double) * (size_t)n * ldr));
     double *cheb64 = nullptr;
     bool zeroed = false;
-    while (fp32 && rmax > target && passes < 4) {
+    while (fp32 && rmax > target && passes < 8) {
       const double tr0 = now_s();
       if (!cheb64)
         cheb64 = static_cast<double *>(ctx->buf("cheb64").ensure(sizeof(double) * 3 * (size_t)n * 64));
@@ -793,7 +834,7 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
       if (verbose)
         fprintf(stderr, "[polfed] refine pass %d: K_r %lld, %d vectors, max resid / ||H|| = %.3e\n",
                 passes, K_r, q, rmax / normH);
-      K_r = std::min<long long>(2 * K_r, K);
+      K_r = std::min<long long>(2 * K_r, K_ref);
     }
   }
   if (evecs) {
@@ -803,6 +844,8 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
   }
   PF_HIP(hipStreamSynchronize(st));
   double t_rr = now_s() - t3 - t_refine;
+  filter_gpu_s += ctx->filter_gpu_s - ctx_gpu0;
+  filter_launches += ctx->filter_launches - ctx_launch0;
 
   for (int i = 0; i < nout; ++i) {
     evals[i] = Esel[i];
@@ -840,10 +883,254 @@ static int solve_impl(polfed_ctx *ctx, const Chain &c, const polfed_opts &o, int
   inf.t_total = now_s() - t_start;
   inf.hv_apps = (double)(K + 1) * ms + rr_apps + o.bounds_steps;
   inf.filter_bytes = bytes + refine_bytes;
-  inf.filter_gpu_s = ctx->filter_gpu_s;
-  inf.filter_launches = ctx->filter_launches;
+  inf.filter_gpu_s = filter_gpu_s;
+  inf.filter_launches = filter_launches;
   if (info) *info = inf;
   return (converged && nout == nev) ? POLFED_OK : POLFED_NOT_CONVERGED;
+}
+
+
+// ------------------------------------------------------------- drivers --
+
+template <class T>
+static int solve_single(polfed_ctx *ctx, const polfed_model *model, const polfed_opts &o, int nev,
+                        double *evals, double *evecs, double *resid, polfed_info *info) {
+  Realization<T> R;
+  R.setup(ctx, model, o, nev);
+  T *cheb = static_cast<T *>(ctx->buf("cheb").ensure(sizeof(T) * 3 * (size_t)R.n * R.s));
+  while (!R.done) {
+    const double t0 = now_s();
+    const double g0 = ctx->filter_gpu_s, l0 = ctx->filter_launches;
+    const T *X = R.filter_X();
+    run_filter<T>(ctx, R.c, R.dt(), R.a, R.s, X, R.s, R.Ys(), R.s, R.K, R.coef, R.D, cheb,
+                  R.fp32, &R.bytes);
+    R.filter_gpu_s += ctx->filter_gpu_s - g0;
+    R.filter_launches += ctx->filter_launches - l0;
+    R.t_filter += now_s() - t0;
+    R.lanczos_step();
+  }
+  return R.finalize(evals, evecs, resid, info);
+}
+
+// Residual bar of returned pairs in FP32-filter mode: a result whose FP64
+// refinement could not bring every residual to 1e-8 ||H|| (this happens when
+// the Gaussian density of states overestimated the window, so that wanted
+// values sit below p where the filter separates them poorly) is recomputed
+// with the FP64 filter; info->refine_passes is then -1.
+constexpr double kFp32ResidBar = 1e-8;
+
+static int fp64_resolve(polfed_ctx *ctx, const polfed_model *model, const polfed_opts &o, int nev,
+                        double *evals, double *evecs, double *resid, polfed_info *info,
+                        const polfed_info &first) {
+  polfed_opts o64 = o;
+  o64.precision = 0;
+  polfed_info i64;
+  const int rc = solve_single<double>(ctx, model, o64, nev, evals, evecs, resid, &i64);
+  i64.refine_passes = -1;
+  i64.t_total += first.t_total;
+  i64.t_refine += first.t_total;  // the abandoned FP32 attempt
+  i64.hv_apps += first.hv_apps;
+  i64.filter_bytes += first.filter_bytes;
+  i64.filter_gpu_s += first.filter_gpu_s;
+  i64.filter_launches += first.filter_launches;
+  if (info) *info = i64;
+  return rc;
+}
+
+int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opts_in, int nev,
+              double *evals, double *evecs, double *resid, polfed_info *info) {
+  polfed_opts o = resolve_opts(opts_in);
+  PF_REQUIRE(evals != nullptr && resid != nullptr, "evals and resid must not be NULL");
+  if (o.precision == 1) {
+    polfed_info i32;
+    const int rc = solve_single<float>(ctx, model, o, nev, evals, evecs, resid, &i32);
+    if (i32.max_resid > kFp32ResidBar * i32.normH)
+      return fp64_resolve(ctx, model, o, nev, evals, evecs, resid, info, i32);
+    if (info) *info = i32;
+    return rc;
+  }
+  return solve_single<double>(ctx, model, o, nev, evals, evecs, resid, info);
+}
+
+// Batched solve: realisations are grouped by chain length (and block size);
+// each group advances in lock step, one Lanczos block at a time, with the
+// filter of all its active members in one persistent launch per Chebyshev
+// step (k_step_batched), the K_max + 1 launches of a block captured once in
+// a HIP graph and replayed for every block.  Members whose order K_i is
+// below K_max idle for the first K_max - K_i steps; members that converged
+// are switched off in the device descriptor table.
+template <class T>
+static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
+                            const polfed_opts &o, int nev, double *evals, double *evecs,
+                            double *resid, polfed_info *infos, int *status) {
+  hipStream_t st = ctx->stream;
+  // evecs offsets of every realisation
+  std::vector<size_t> voff(R + 1, 0);
+  for (int r = 0; r < R; ++r) {
+    const long long d = polfed_dim(models[r].L);
+    PF_REQUIRE(d > 0, "invalid L in batch");
+    voff[r + 1] = voff[r] + (size_t)d * nev;
+  }
+  // group by (L, block size)
+  std::map<std::pair<int, int>, std::vector<int>> groups;
+  for (int r = 0; r < R; ++r) {
+    validate_model(&models[r]);
+    const int s = o.block_size ? o.block_size : choose_block(models[r].L, nev, o.precision);
+    groups[{models[r].L, s}].push_back(r);
+  }
+  int worst = POLFED_OK;
+  for (auto &g : groups) {
+    const std::vector<int> &mem = g.second;
+    const int B = (int)mem.size();
+    const double tg0 = now_s();
+    std::vector<std::unique_ptr<Realization<T>>> rs(B);
+    polfed_opts og = o;
+    og.block_size = g.first.second;
+    long long Kmax = 0;
+    for (int i = 0; i < B; ++i) {
+      rs[i].reset(new Realization<T>());
+      rs[i]->setup(ctx, &models[mem[i]], og, nev);
+      Kmax = std::max(Kmax, rs[i]->K);
+    }
+    const Realization<T> &r0 = *rs[0];
+    const long long n = r0.n;
+    const int S = r0.s;
+    // per-member recurrence buffers, coefficients and descriptors
+    DevBuf cheb, coefs, itemsd;
+    cheb.ensure(sizeof(T) * 3 * (size_t)n * S * B);
+    size_t ncoef = 0;
+    for (auto &r : rs) ncoef += r->coef.size();
+    coefs.ensure(sizeof(double) * ncoef);
+    std::vector<BatchItem<T>> items(B);
+    size_t co = 0;
+    for (int i = 0; i < B; ++i) {
+      Realization<T> &r = *rs[i];
+      PF_HIP(hipMemcpyAsync(coefs.as<double>() + co, r.coef.data(), sizeof(double) * r.coef.size(),
+                            hipMemcpyHostToDevice, st));
+      BatchItem<T> &it = items[i];
+      it.dt = r.dt();
+      it.X = r.Xs();
+      it.buf = cheb.as<T>() + (size_t)3 * n * S * i;
+      it.Y = r.Ys();
+      it.coef = coefs.as<double>() + co;
+      it.Dinv = 1.0 / r.D;
+      it.w1 = (T)(r.a * r.c.J1);
+      it.w2 = (T)(r.a * r.c.J2);
+      it.K = r.K;
+      it.active = 1;
+      co += r.coef.size();
+    }
+    itemsd.ensure(sizeof(BatchItem<T>) * B);
+    StepArgs<T> base = base_args<T>(r0.c, r0.dt());
+    const StepShape shape = shape_for(ctx, r0.c.L, S, r0.fp32);
+    hipGraphExec_t graph = nullptr;
+    hipEvent_t e0, e1;
+    PF_HIP(hipEventCreate(&e0));
+    PF_HIP(hipEventCreate(&e1));
+    double gfilter = 0.0, gbytes = 0.0, glaunch = 0.0;
+    try {
+      for (;;) {
+        int nact = 0;
+        for (int i = 0; i < B; ++i) {
+          items[i].active = rs[i]->done ? 0 : 1;
+          if (!rs[i]->done) {
+            rs[i]->filter_X();
+            ++nact;
+          }
+        }
+        if (nact == 0) break;
+        PF_HIP(hipMemcpyAsync(itemsd.p, items.data(), sizeof(BatchItem<T>) * B,
+                              hipMemcpyHostToDevice, st));
+        if (!graph && ctx->use_graphs && Kmax <= (1LL << 17)) {
+          hipGraph_t gr = nullptr;
+          PF_HIP(hipStreamBeginCapture(ctx->own_stream, hipStreamCaptureModeThreadLocal));
+          try {
+            for (long long j = 0; j <= Kmax; ++j)
+              launch_step_batched<T>(ctx->own_stream, S, base, itemsd.as<BatchItem<T>>(), B, j, Kmax,
+                                     shape, ctx->num_cu);
+          } catch (...) {
+            hipGraph_t dummy = nullptr;
+            (void)hipStreamEndCapture(ctx->own_stream, &dummy);
+            if (dummy) (void)hipGraphDestroy(dummy);
+            throw;
+          }
+          PF_HIP(hipStreamEndCapture(ctx->own_stream, &gr));
+          hipError_t e = hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          PF_HIP(e);
+        }
+        const double tf0 = now_s();
+        PF_HIP(hipEventRecord(e0, st));
+        if (graph) {
+          PF_HIP(hipGraphLaunch(graph, st));
+        } else {
+          for (long long j = 0; j <= Kmax; ++j)
+            launch_step_batched<T>(st, S, base, itemsd.as<BatchItem<T>>(), B, j, Kmax, shape,
+                                   ctx->num_cu);
+        }
+        PF_HIP(hipEventRecord(e1, st));
+        PF_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        PF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        gfilter += 1e-3 * ms;
+        glaunch += (double)(Kmax + 1);
+        // algorithmic bytes of the active members (same model as one filter)
+        for (int i = 0; i < B; ++i) {
+          if (!items[i].active) continue;
+          const long long K = rs[i]->K;
+          double mv = 0.0;
+          for (long long jj = 0; jj < K; ++jj) {
+            const int streams = 1 + (jj >= 1) + (jj >= 2) + (rs[i]->coef[K - jj] != 0.0);
+            mv += (double)n * (S * (double)sizeof(T) * streams + (jj >= 1 ? 4.0 + sizeof(T) : 0.0));
+          }
+          mv += (double)n * (S * (double)sizeof(T) * (2 + (K >= 1) + (K >= 2)) +
+                             (K >= 1 ? 4.0 + sizeof(T) : 0.0));
+          gbytes += mv;
+          rs[i]->bytes += mv;
+        }
+        const double tf = now_s() - tf0;
+        for (int i = 0; i < B; ++i)
+          if (items[i].active) rs[i]->t_filter += tf / nact;
+        for (int i = 0; i < B; ++i)
+          if (items[i].active) rs[i]->lanczos_step();
+      }
+    } catch (...) {
+      if (graph) (void)hipGraphExecDestroy(graph);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    if (graph) PF_HIP(hipGraphExecDestroy(graph));
+    PF_HIP(hipEventDestroy(e0));
+    PF_HIP(hipEventDestroy(e1));
+    for (int i = 0; i < B; ++i) {
+      const int r = mem[i];
+      rs[i]->filter_gpu_s = gfilter / B;
+      rs[i]->filter_launches = glaunch / B;
+      polfed_info ir;
+      int rc = rs[i]->finalize(evals + (size_t)r * nev, evecs ? evecs + voff[r] : nullptr,
+                               resid + (size_t)r * nev, &ir);
+      if (rs[i]->fp32 && ir.max_resid > kFp32ResidBar * ir.normH)
+        rc = fp64_resolve(ctx, &models[r], og, nev, evals + (size_t)r * nev,
+                          evecs ? evecs + voff[r] : nullptr, resid + (size_t)r * nev, &ir, ir);
+      if (infos) infos[r] = ir;
+      status[r] = rc;
+      if (rc > 0 && worst == POLFED_OK) worst = rc;
+    }
+    (void)tg0;
+    (void)gbytes;
+  }
+  return worst;
+}
+
+int solve_batch(polfed_ctx *ctx, int R, const polfed_model *models, const polfed_opts *opts_in,
+                int nev, double *evals, double *evecs, double *resid, polfed_info *infos,
+                int *status) {
+  polfed_opts o = resolve_opts(opts_in);
+  PF_REQUIRE(R >= 1 && models && status && evals && resid, "invalid batch arguments");
+  if (o.precision == 1)
+    return solve_batch_impl<float>(ctx, R, models, o, nev, evals, evecs, resid, infos, status);
+  return solve_batch_impl<double>(ctx, R, models, o, nev, evals, evecs, resid, infos, status);
 }
 
 // ------------------------------------------------- stage-call helpers --
