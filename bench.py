@@ -54,15 +54,16 @@ def _traffic(workload):
         return None
 
 
-def _cpu_baseline(wl, target_s=15.0):
+def _cpu_baseline(wl, target_s=15.0, blocks=None):
     """The oracle's forward-recurrence filter (scipy CSR, FP64) on the
-    workload's block shape, timed on the host for ~target_s seconds."""
+    workload's block shape (its first chain), timed on the host for
+    ~target_s seconds."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import chain, chebyshev
     c = wl.chains[0]
     H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
-    s = wl.block if wl.block > 0 else 16
+    s = wl.block if wl.block > 0 else (blocks[-1] if blocks else 16)
     X = np.random.default_rng(0).standard_normal((H.shape[0], s))
     E0, E1 = -2.0 * c.L, 2.0 * c.L  # any enclosing interval: cost is independent of it
     with threadpool_limits(1):
@@ -83,7 +84,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3_fp64", "c3_fp32"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3_fp64", "c3_fp32", "c4"])
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the step shape first (outside the timed region); workloads "
+                         "without a fixed block size always tune it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     args = ap.parse_args()
@@ -97,16 +101,35 @@ def main():
     from paper_2005_09534_amd import workloads
 
     wl = {"c1": workloads.c1, "c2": workloads.c2, "c3_fp64": lambda: workloads.c3("fp64"),
-          "c3_fp32": lambda: workloads.c3("fp32")}[args.workload]()
+          "c3_fp32": lambda: workloads.c3("fp32"), "c4": workloads.c4}[args.workload]()
     c = wl.chains[0]
     prec = 1 if wl.precision == "fp32" else 0
     ctx = pf.Context(0)
-    model = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
+    models = [pf.make_model(ch.L, ch.J1, ch.J2, ch.Delta, ch.h) for ch in wl.chains]
+    model = models[0]
     opts = pf.default_opts(block_size=wl.block, K=wl.K, precision=prec, target_kind=0,
                            target=wl.eps_target)
+    tune_s = 0.0
+    if args.tune or wl.block == 0:  # a workload without a fixed block size is autotuned
+        from paper_2005_09534_amd import autotune
+        t0 = time.perf_counter()
+        by_L = {}
+        for ch in wl.chains:
+            by_L.setdefault(ch.L, []).append(ch)
+        for L, chs in sorted(by_L.items()):
+            if wl.block == 0:
+                # a sample of this length (batch throughput when batched)
+                autotune.tune_block(ctx, chs[:8] if len(models) > 1 else chs[0], wl.nev, prec)
+            else:
+                autotune.tune_shape(ctx, chs[0], wl.block, prec)
+        tune_s = time.perf_counter() - t0
 
     def step():
-        return ctx.solve(model, wl.nev, opts=opts, vectors=True)
+        if len(models) == 1:
+            r = ctx.solve(model, wl.nev, opts=opts, vectors=True)
+            return r, [r["info"]], [r["status"]]
+        r = ctx.solve_batch(models, wl.nev, opts=opts, vectors=True)
+        return r, r["info"], r["status"]
 
     for _ in range(args.warmup):
         step()
@@ -114,10 +137,11 @@ def main():
     t0 = time.perf_counter()
     infos = []
     for _ in range(args.steps):
-        r = step()
-        infos.append(r["info"])
-        if r["status"] != pf.OK:
-            print(f"warning: solve status {r['status']}", file=sys.stderr)
+        r, inf, sts = step()
+        infos.extend(inf)
+        bad = [x for x in sts if x != pf.OK]
+        if bad:
+            print(f"warning: {len(bad)} solves with status != OK", file=sys.stderr)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
@@ -140,14 +164,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec else "f64",
         "data": "synthetic",
-        "config": {"workload": wl.name, "L": c.L, "dim": pf.dim(c.L), "J2": c.J2,
-                   "Delta": c.Delta, "W": c.W, "nev": wl.nev, "block": last["block_size"],
-                   "K": last["K"], "lanczos_blocks": last["m"],
-                   "precision": wl.precision},
+        "config": {"workload": wl.name, "realisations": len(models),
+                   "L": sorted(set(ch.L for ch in wl.chains)),
+                   "dim": [pf.dim(L) for L in sorted(set(ch.L for ch in wl.chains))],
+                   "J2": c.J2, "Delta": c.Delta, "W": sorted(set(ch.W for ch in wl.chains)),
+                   "nev": wl.nev, "block": sorted(set(i["block_size"] for i in infos)),
+                   "K": last["K"] if len(models) == 1 else [min(i["K"] for i in infos), max(i["K"] for i in infos)],
+                   "lanczos_blocks": last["m"] if len(models) == 1 else [min(i["m"] for i in infos), max(i["m"] for i in infos)],
+                   "precision": wl.precision, "autotune_s": tune_s},
         "time_to_nev_s": wall / args.steps,
         "solve": {k: last[k] for k in ("t_bounds", "t_filter", "t_orth", "t_eig", "t_rr",
                                        "t_refine", "t_total", "max_resid", "normH", "n_conv",
                                        "refine_passes")},
+        "max_resid_rel": max(i["max_resid"] / i["normH"] for i in infos),
         "roofline": {
             "kernel": "k_step (fused Chebyshev step: matrix-free H~ gather + 3-term update)",
             "bound": "hbm",
@@ -161,7 +190,7 @@ def main():
             "launches": flaunch,
         },
     }
-    if not args.no_fp32 and prec == 0:
+    if not args.no_fp32 and prec == 0 and len(models) == 1:
         o32 = pf.default_opts(block_size=wl.block, K=wl.K, precision=1, target_kind=0,
                               target=wl.eps_target)
         ctx.solve(model, wl.nev, opts=o32, vectors=True)  # warm
@@ -177,7 +206,7 @@ def main():
             "max_abs_eval_diff_vs_fp64": float(abs(r32["E"] - r["E"]).max()),
             "status": r32["status"]}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = _cpu_baseline(wl)
+        line["cpu_baseline"] = _cpu_baseline(wl, blocks=line["config"]["block"])
     ctx.close()
     print(json.dumps(line), flush=True)
 

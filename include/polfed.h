@@ -201,6 +201,11 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *model, int steps,
  * The autotuner (paper_2005_09534_amd/autotune.py) searches this space. */
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads,
                           int lpl, int wg_per_cu, int lds_tables);
+/* Block size used when opts->block_size is 0 for chains of length L at the
+ * given precision and N_ev (the autotuner's choice); without an entry a
+ * built-in rule is used (about N_ev/4, capped at 16 in FP64 and 32 in FP32,
+ * at 8 for L <= 14). */
+int polfed_set_block_size(polfed_ctx *ctx, int L, int precision, int nev, int block_size);
 /* Capture each filter application (its K+1 step launches) in a HIP graph
  * that is replayed for every Lanczos block (on != 0, the default unless the
  * environment sets POLFED_NO_GRAPH), or launch the steps one by one.  Used

@@ -1,0 +1,134 @@
+"""Autotuner of the POLFED hot path on one GPU.
+
+Two choices are tuned, both through the C ABI of libpolfed:
+
+* the launch shape of the fused Chebyshev-step kernel (threads per group,
+  16-byte loads per lane, persistent groups per CU, rank tables in LDS) for a
+  (chain length L, block width, precision): each candidate applies the
+  filter for a few dozen steps to a random block of the chain and is timed
+  with the library's HIP-event counters; the fastest shape per HBM-second
+  wins (``polfed_set_step_shape``);
+* the Lanczos block size for (L, precision, N_ev): a sample of realisations
+  (one, or a batch of a few of the same L) is solved with each candidate
+  width and the shortest time to N_ev per realisation wins
+  (``polfed_set_block_size``).
+
+Results are cached as JSON (default: $POLFED_TUNE_CACHE, else
+~/.cache/polfed_tune.json) keyed by "shape:L:J2nonzero:precision:width" and
+"block:L:J2nonzero:precision:nev", and re-applied by ``apply_cache``.
+"""
+
+import itertools
+import json
+import os
+import time
+
+SHAPES = [(t, lpl, wpc, lds) for t, lpl, wpc, lds in
+          itertools.product((256, 1024), (1, 2, 4), (1, 2, 4, 8, 16), (1, 0))
+          if not (t == 1024 and wpc > 2)]
+
+
+def cache_path():
+    return os.environ.get("POLFED_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "polfed_tune.json"))
+
+
+def load_cache(path=None):
+    path = path or cache_path()
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(cache, path=None):
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def _key(kind, L, J2, precision, x):
+    return f"{kind}:{L}:{int(J2 != 0.0)}:{precision}:{x}"
+
+
+def tune_shape(ctx, chain, width, precision, steps=None, shapes=SHAPES, cache=None):
+    """Fastest step-kernel shape for the chain's L at this width/precision.
+    Leaves it set on ctx; returns (shape, GB/s)."""
+    import torch
+    from . import polfed as pf
+    m = pf.make_model(chain.L, chain.J1, chain.J2, chain.Delta, chain.h)
+    n = pf.dim(chain.L)
+    dt = torch.float32 if precision else torch.float64
+    X = torch.randn((n, width), device="cuda", dtype=torch.float64).to(dt)
+    Y = torch.empty_like(X)
+    if steps is None:
+        steps = max(8, min(200, int(2e9 / (n * width * (4 if precision else 8) * 4))))
+    E0, E1 = -2.0 * chain.L, 2.0 * chain.L  # any enclosing interval; cost is independent of it
+    best = None
+    for sh in shapes:
+        ctx.set_step_shape(chain.L, width, precision, *sh)
+        ctx.apply_filter(m, E0, E1, 0.0, 2, X, out=Y)
+        ctx.filter_stats(reset=True)
+        ctx.apply_filter(m, E0, E1, 0.0, steps, X, out=Y)
+        st = ctx.filter_stats(reset=True)
+        gbs = st["bytes"] / st["gpu_s"] / 1e9
+        if best is None or gbs > best[1]:
+            best = (sh, gbs)
+    ctx.set_step_shape(chain.L, width, precision, *best[0])
+    if cache is not None:
+        cache[_key("shape", chain.L, chain.J2, precision, width)] = list(best[0]) + [best[1]]
+    return best
+
+
+def tune_block(ctx, chains, nev, precision, widths=(4, 8, 16, 32), cache=None, shape_cache=None):
+    """Block size with the shortest time to nev per realisation.
+
+    `chains` is one chain or a list of chains of one length L: a list is
+    solved as one batch (polfed_solve_batch), so the choice reflects batch
+    throughput rather than the latency of a single solve.  Tunes the step
+    shape of each width first.  Leaves the choice set on ctx; returns
+    (block, seconds per realisation) or None when no width converged."""
+    import torch
+    from . import polfed as pf
+    if not isinstance(chains, (list, tuple)):
+        chains = [chains]
+    L = chains[0].L
+    if any(c.L != L for c in chains):
+        raise ValueError("tune_block: chains of one length only")
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in chains]
+    best = None
+    for s in widths:
+        if s > nev * 2:
+            continue
+        tune_shape(ctx, chains[0], s, precision, cache=shape_cache)
+
+        def run():
+            if len(models) == 1:
+                r = ctx.solve(models[0], nev, block_size=s, precision=precision, vectors=False)
+                return [r["status"]]
+            return ctx.solve_batch(models, nev, block_size=s, precision=precision,
+                                   vectors=False)["status"]
+        run()  # warm (graph capture, buffers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = run()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / len(models)
+        if all(x == pf.OK for x in st) and (best is None or t < best[1]):
+            best = (s, t)
+    if best is not None:
+        ctx.set_block_size(L, precision, nev, best[0])
+        if cache is not None:
+            cache[_key("block", L, chains[0].J2, precision, nev)] = [best[0], best[1]]
+    return best
+
+
+def apply_cache(ctx, cache):
+    """Set every cached shape and block size on ctx."""
+    for k, v in cache.items():
+        kind, L, _j2, prec, x = k.split(":")
+        if kind == "shape":
+            ctx.set_step_shape(int(L), int(x), int(prec), *[int(t) for t in v[:4]])
+        elif kind == "block":
+            ctx.set_block_size(int(L), int(prec), int(x), int(v[0]))

@@ -342,6 +342,17 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
   });
 }
 
+int polfed_set_block_size(polfed_ctx *ctx, int L, int precision, int nev, int block_size) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
+    PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
+    PF_REQUIRE(nev >= 1, "nev must be >= 1");
+    PF_REQUIRE(pow2_block(block_size), "block_size must be a power of two in [1, 64]");
+    ctx->blocks[std::make_tuple(L, precision, nev)] = block_size;
+    return POLFED_OK;
+  });
+}
+
 int polfed_set_graphs(polfed_ctx *ctx, int on) {
   return guarded(ctx, [&] {
     ctx->use_graphs = on ? 1 : 0;

@@ -244,6 +244,8 @@ struct polfed_ctx {
   // launch shapes of the step kernel chosen by the autotuner, keyed by
   // (L, block width, precision bytes)
   std::map<std::tuple<int, int, int>, polfed::StepShape> shapes;
+  // block sizes chosen by the autotuner, keyed by (L, precision, nev)
+  std::map<std::tuple<int, int, int>, int> blocks;
   // cached HIP graph of one whole filter application (K+1 step launches),
   // replayed for every Lanczos block; keyed by everything baked into it
   hipGraphExec_t filter_graph = nullptr;

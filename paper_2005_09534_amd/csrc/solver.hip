@@ -336,6 +336,14 @@ static int next_pow2_le(int x) {
 
 int choose_block(int L, int nev, int precision);
 
+// Block size: the autotuner's entry for (L, precision, nev) if the context
+// holds one, else the built-in rule.
+static int block_for(const polfed_ctx *ctx, int L, int nev, int precision) {
+  auto it = ctx->blocks.find(std::make_tuple(L, precision, nev));
+  if (it != ctx->blocks.end()) return it->second;
+  return choose_block(L, nev, precision);
+}
+
 static polfed_opts resolve_opts(const polfed_opts *in) {
   polfed_opts o;
   polfed_default_opts(&o);
@@ -404,7 +412,7 @@ void Realization<T>::setup(polfed_ctx *ctx_, const polfed_model *model, const po
   make_chain(ctx, model, c);
   n = c.basis->n;
   PF_REQUIRE(nev >= 1 && nev <= n, "nev must be in [1, dim]");
-  if (o.block_size == 0) o.block_size = choose_block(c.L, nev, o.precision);
+  if (o.block_size == 0) o.block_size = block_for(ctx, c.L, nev, o.precision);
   PF_REQUIRE(o.block_size >= 1 && o.block_size <= 64 &&
                  (o.block_size & (o.block_size - 1)) == 0,
              "block_size must be a power of two in [1, 64]");
@@ -975,7 +983,7 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int r = 0; r < R; ++r) {
     validate_model(&models[r]);
-    const int s = o.block_size ? o.block_size : choose_block(models[r].L, nev, o.precision);
+    const int s = o.block_size ? o.block_size : block_for(ctx, models[r].L, nev, o.precision);
     groups[{models[r].L, s}].push_back(r);
   }
   int worst = POLFED_OK;

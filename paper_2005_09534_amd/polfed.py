@@ -89,6 +89,7 @@ def _load():
         "polfed_set_step_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int,
                                           c_int]),
         "polfed_set_graphs": (c_int, [c_void_p, c_int]),
+        "polfed_set_block_size": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
         "polfed_filter_stats": (c_int, [c_void_p, P_double, P_double, P_double, c_int]),
         "polfed_solve": (c_int, [c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts), c_int,
                                  P_double, P_double, P_double, ctypes.POINTER(Info)]),
@@ -274,6 +275,10 @@ class Context:
     def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1):
         self._check(LIB.polfed_set_step_shape(self.h, L, nvec, precision, threads, lpl, wg_per_cu,
                                               lds_tables), "set_step_shape")
+
+    def set_block_size(self, L, precision, nev, block_size):
+        self._check(LIB.polfed_set_block_size(self.h, L, precision, nev, block_size),
+                    "set_block_size")
 
     def set_graphs(self, on):
         self._check(LIB.polfed_set_graphs(self.h, int(bool(on))), "set_graphs")

@@ -1,0 +1,63 @@
+"""Autotuner on the GPU: every step shape computes the same filter bit for
+bit (a row's arithmetic does not depend on the launch shape), the tuned
+shape is kept, and a tuned block size is used by solves that ask for one."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2005_09534_amd import workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_09534_amd import polfed as pf
+    c = pf.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("precision,width", [(0, 8), (1, 32)])
+def test_shapes_bitwise_identical(ctx, precision, width):
+    from paper_2005_09534_amd import autotune, polfed as pf
+    c = workloads.chain(14, 2.0, 7)
+    m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
+    n = pf.dim(c.L)
+    dt = torch.float32 if precision else torch.float64
+    X = torch.from_numpy(workloads.random_block(n, width, 3)).to("cuda").to(dt)
+    E0, E1, r0, r1 = ctx.bounds(m, 100)
+    w = E1 - E0
+    E0w, E1w = E0 - r0 - 1e-3 * w, E1 + r1 + 1e-3 * w
+    ref = None
+    for sh in autotune.SHAPES[::3]:
+        ctx.set_step_shape(c.L, width, precision, *sh)
+        Y = ctx.apply_filter(m, E0w, E1w, 0.0, 40, X)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = Y.clone()
+        else:
+            assert torch.equal(Y, ref), sh
+
+
+def test_tune_shape_and_block(ctx):
+    from paper_2005_09534_amd import autotune, polfed as pf
+    chains = [workloads.chain(10, 2.0, 50 + i) for i in range(3)]
+    cache = {}
+    sh, gbs = autotune.tune_shape(ctx, chains[0], 4, 0, steps=8, shapes=autotune.SHAPES[:4],
+                                  cache=cache)
+    assert sh in autotune.SHAPES[:4] and gbs > 0
+    best = autotune.tune_block(ctx, chains, 6, 0, widths=(2, 4), cache=cache)
+    assert best is not None and best[0] in (2, 4)
+    assert cache[autotune._key("block", 10, 0.0, 0, 6)][0] == best[0]
+    m = pf.make_model(chains[1].L, chains[1].J1, chains[1].J2, chains[1].Delta, chains[1].h)
+    r = ctx.solve(m, 6, block_size=0, precision=0, vectors=False)
+    assert r["status"] == pf.OK
+    assert r["info"]["block_size"] == best[0]
+    rb = ctx.solve_batch([m, m], 6, block_size=0, precision=0)
+    assert [i["block_size"] for i in rb["info"]] == [best[0]] * 2
+    np.testing.assert_array_equal(rb["E"][0], rb["E"][1])
