@@ -3,7 +3,8 @@
 Two choices are tuned, both through the C ABI of libpolfed:
 
 * the launch shape of the fused Chebyshev-step kernel (threads per group,
-  16-byte loads per lane, persistent groups per CU, rank tables in LDS) for a
+  16-byte loads per lane, persistent groups per CU, rank tables in LDS, one
+  launch per step or one cooperative launch for all steps) for a
   (chain length L, block width, precision): each candidate applies the
   filter for a few dozen steps to a random block of the chain and is timed
   with the library's HIP-event counters; the fastest shape per HBM-second
@@ -23,9 +24,11 @@ import json
 import os
 import time
 
-SHAPES = [(t, lpl, wpc, lds) for t, lpl, wpc, lds in
-          itertools.product((256, 1024), (1, 2, 4), (1, 2, 4, 8, 16), (1, 0))
-          if not (t == 1024 and wpc > 2)]
+# (threads, 16-byte loads per lane, groups per CU, LDS rank tables, fused
+# cooperative launch of all steps)
+SHAPES = [(t, lpl, wpc, lds, fused) for t, lpl, wpc, lds, fused in
+          itertools.product((256, 1024), (1, 2, 4), (1, 2, 4, 8, 16), (1, 0), (0, 1))
+          if not (t == 1024 and wpc > 2) and not (fused and (t == 1024 or wpc > 4))]
 
 
 def cache_path():
@@ -78,6 +81,7 @@ def tune_shape(ctx, chain, width, precision, steps=None, shapes=SHAPES, cache=No
     ctx.set_step_shape(chain.L, width, precision, *best[0])
     if cache is not None:
         cache[_key("shape", chain.L, chain.J2, precision, width)] = list(best[0]) + [best[1]]
+
     return best
 
 
@@ -129,6 +133,6 @@ def apply_cache(ctx, cache):
     for k, v in cache.items():
         kind, L, _j2, prec, x = k.split(":")
         if kind == "shape":
-            ctx.set_step_shape(int(L), int(x), int(prec), *[int(t) for t in v[:4]])
+            ctx.set_step_shape(int(L), int(x), int(prec), *[int(t) for t in v[:5]])
         elif kind == "block":
             ctx.set_block_size(int(L), int(prec), int(x), int(v[0]))

@@ -111,8 +111,16 @@ void polfed_default_opts(polfed_opts *o) {
   o->seed = 12345;
 }
 
+// Message of the last failed polfed_create on this host thread (there is no
+// context to hold it).
+static thread_local std::string t_create_error;
+
 int polfed_create(int device, polfed_ctx **out) {
-  if (!out) return POLFED_EINVAL;
+  t_create_error.clear();
+  if (!out) {
+    t_create_error = "polfed_create: out is NULL";
+    return POLFED_EINVAL;
+  }
   *out = nullptr;
   polfed_ctx *ctx = new polfed_ctx();
   ctx->device = device;
@@ -121,18 +129,25 @@ int polfed_create(int device, polfed_ctx **out) {
     PF_HIP(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) {
       delete ctx;
+      t_create_error = "polfed_create: device " + std::to_string(device) + " out of range (" +
+                       std::to_string(ndev) + " visible)";
       return POLFED_EINVAL;
     }
     PF_HIP(hipSetDevice(device));
     hipDeviceProp_t prop;
     PF_HIP(hipGetDeviceProperties(&prop, device));
     ctx->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    int wc_khz = 0;
+    if (hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess &&
+        wc_khz > 0)
+      ctx->wall_clock_hz = 1e3 * wc_khz;
     PF_HIP(hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
     ctx->stream = ctx->own_stream;
     ctx->use_graphs = std::getenv("POLFED_NO_GRAPH") ? 0 : 1;
     upload_binomials(device);
   } catch (const Error &e) {
     delete ctx;
+    t_create_error = e.what();
     return e.code;
   }
   *out = ctx;
@@ -154,7 +169,7 @@ int polfed_destroy(polfed_ctx *ctx) {
 }
 
 const char *polfed_last_error(const polfed_ctx *ctx) {
-  return ctx ? ctx->last_error.c_str() : "null context";
+  return ctx ? ctx->last_error.c_str() : t_create_error.c_str();
 }
 
 int polfed_set_stream(polfed_ctx *ctx, void *stream) {
@@ -324,7 +339,7 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *m, int steps, unsigned lo
 }
 
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads, int lpl,
-                          int wg_per_cu, int lds_tables) {
+                          int wg_per_cu, int lds_tables, int fused) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
     PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
@@ -337,6 +352,7 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
     sh.lpl = lpl;
     sh.wg_per_cu = wg_per_cu;
     sh.lds_tables = lds_tables ? 1 : 0;
+    sh.fused = fused ? 1 : 0;
     ctx->shapes[std::make_tuple(L, nvec, precision ? 4 : 8)] = sh;
     return POLFED_OK;
   });

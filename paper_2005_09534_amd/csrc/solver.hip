@@ -136,7 +136,9 @@ static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shap
   st.ldo = ldy;
   st.X = X;
   st.ldx = ldx;
-  st.alpha = (T)(coef[0] / D);
+  // (same rounding as the fused kernel: products with 1/D)
+  const double Dinv = 1.0 / D;
+  st.alpha = (T)(coef[0] * Dinv);
   if (K >= 1) {
     st.V = bufs[(K - 1) % 3];
     st.ldv = S;
@@ -145,10 +147,10 @@ static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shap
     st.W = bufs[(K - 2) % 3];
     st.ldw = S;
   }
-  st.dscale = (T)(1.0 / D);
-  st.w1 = (T)(a * c.J1 / (2.0 * D));
-  st.w2 = (T)(a * c.J2 / (2.0 * D));
-  st.gamma = (T)(-1.0 / D);
+  st.dscale = (T)Dinv;
+  st.w1 = (T)(0.5 * (a * c.J1) * Dinv);
+  st.w2 = (T)(0.5 * (a * c.J2) * Dinv);
+  st.gamma = (T)(-Dinv);
   launch_step<T>(stream, S, st, shape, num_cu);
   const int streams = 2 + (st.V ? 1 : 0) + (st.W ? 1 : 0);
   moved += (double)n * (S * bpv * streams + (st.V ? 4.0 + bpv : 0.0));
@@ -174,6 +176,57 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
     PF_HIP(hipEventCreate(&ctx->ev_stop));
   }
   double moved = 0.0;
+  // algorithmic bytes of the K + 1 steps (same model as queue_filter)
+  auto step_bytes = [&]() {
+    double mv = 0.0;
+    for (long long j = 0; j < K; ++j) {
+      const int streams = 1 + (j >= 1) + (j >= 2) + (coef[K - j] != 0.0);
+      mv += (double)n * (S * (double)sizeof(T) * streams + (j >= 1 ? 4.0 + sizeof(T) : 0.0));
+    }
+    mv += (double)n * (S * (double)sizeof(T) * (2 + (K >= 1) + (K >= 2)) +
+                       (K >= 1 ? 4.0 + sizeof(T) : 0.0));
+    return mv;
+  };
+  if (shape.fused && K >= 1) {
+    // one cooperative launch for all K + 1 steps
+    double *coefd = static_cast<double *>(ctx->buf("fused_coef").ensure(sizeof(double) * (K + 1)));
+    unsigned *sync = static_cast<unsigned *>(ctx->buf("fused_sync").ensure(64));
+    PF_HIP(hipMemcpyAsync(coefd, coef.data(), sizeof(double) * (K + 1), hipMemcpyHostToDevice,
+                          ctx->stream));
+    launch_fill(ctx->stream, reinterpret_cast<double *>(sync), 1, 0.0);
+    FusedArgs<T> f;
+    f.base = base_args<T>(c, dt);
+    f.X = X;
+    f.ldx = ldx;
+    f.Y = Y;
+    f.ldy = ldy;
+    f.buf = buf3;
+    f.coef = coefd;
+    f.K = K;
+    f.Dinv = 1.0 / D;
+    f.w1 = a * c.J1;
+    f.w2 = a * c.J2;
+    f.sync = sync;
+    f.timeout_ticks = (unsigned long long)(2.0 * ctx->wall_clock_hz);  // 2 s per barrier
+    PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
+    if (launch_filter_fused<T>(ctx->stream, S, f, shape, ctx->num_cu)) {
+      moved = step_bytes();
+      if (bytes) *bytes += moved;
+      PF_HIP(hipEventRecord(ctx->ev_stop, ctx->stream));
+      PF_HIP(hipEventSynchronize(ctx->ev_stop));
+      unsigned flag[2] = {0u, 0u};
+      PF_HIP(hipMemcpy(flag, sync, sizeof(flag), hipMemcpyDeviceToHost));
+      if (flag[1] != 0u)
+        throw Error(POLFED_EDEVICE, "fused filter: a grid barrier timed out");
+      float ms = 0.0f;
+      PF_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+      ctx->filter_gpu_s += 1e-3 * ms;
+      ctx->filter_launches += (double)(K + 1);
+      ctx->filter_bytes += moved;
+      return;
+    }
+    // not co-resident with this shape: the step-per-launch path below
+  }
   if (ctx->use_graphs && graph_worthwhile<T>(n, S, K)) {
     // key: every value baked into the launches
     std::vector<unsigned long long> key = {
@@ -226,14 +279,7 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
     PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
     PF_HIP(hipGraphLaunch(ctx->filter_graph, ctx->stream));
     // same byte model as the direct path
-    std::vector<double> none;
-    moved = 0.0;
-    for (long long j = 0; j < K; ++j) {
-      const int streams = 1 + (j >= 1) + (j >= 2) + (coef[K - j] != 0.0);
-      moved += (double)n * (S * (double)sizeof(T) * streams + (j >= 1 ? 4.0 + sizeof(T) : 0.0));
-    }
-    moved += (double)n * (S * (double)sizeof(T) * (2 + (K >= 1) + (K >= 2)) +
-                          (K >= 1 ? 4.0 + sizeof(T) : 0.0));
+    moved = step_bytes();
   } else {
     PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
     moved = queue_filter<T>(ctx->stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
@@ -447,9 +493,13 @@ void Realization<T>::setup(polfed_ctx *ctx_, const polfed_model *model, const po
   cols = std::min<long long>(cols, (n / s) * s);
   m_max = (int)std::max<long long>(1, cols / s);
   P = m_max * s;
-  // convergence threshold on ||B t~||: FP64 filter 1e-10; FP32 filter its
-  // rounding floor ~eps32 sqrt(K)
-  tau = fp32 ? std::max(1e-10, 30.0 * 1.1920929e-7 * std::sqrt((double)K)) : 1e-10;
+  // convergence threshold on ||B t~||: FP64 filter 1e-10; FP32 filter
+  // eps32 sqrt(K), the size of its rounding errors.  The rounding errors are
+  // spread over the whole spectrum and the FP64 refinement removes them in one
+  // short pass; what it removes slowly is mixing with eigenvectors just
+  // outside the window, which only Lanczos convergence itself suppresses, so
+  // the FP32 run is taken down to this level rather than stopped above it.
+  tau = fp32 ? std::max(1e-10, 1.1920929e-7 * std::sqrt((double)K)) : 1e-10;
 
   Qb.ensure(sizeof(double) * (size_t)n * P);
   Tmb.ensure(sizeof(double) * (size_t)P * P);
@@ -779,15 +829,17 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
     if (verbose) fprintf(stderr, "[polfed] rr: %d candidates, max resid / ||H|| = %.3e\n", nc, rmax / normH);
 
     // FP64 refinement of the FP32-filter mode.  The FP32 rounding of the
-    // recurrence leaves errors ~eps32 sqrt(K) in the Ritz vectors, largest
-    // along eigenvectors whose theta is close to theta_i.  Subspace iteration
-    // with the FP64 filter P^{K_r}(H~) on the q candidate Ritz vectors damps
-    // a component at angular distance u from the target by ~1/(K_r u)
-    // relative to the wanted ones (near-window components by theta_k /
-    // theta_i), and Rayleigh-Ritz on the filtered span removes the mixing;
-    // K_r = K/4, K/2, then K, at most 8 passes.  Target: 2e-9 ||H|| (or tol
-    // if looser), 5x under the 1e-8 ||H|| bar for returned residuals.
-    const double target = std::max(o.tol, 2e-9) * normH;
+    // recurrence leaves errors ~eps32 sqrt(K) in the Ritz vectors, spread
+    // over the whole spectrum.  Subspace iteration with the FP64 filter
+    // P^{K_r}(H~) on the q candidate Ritz vectors damps a component at
+    // angular distance u from the target by ~1/(K_r u) relative to the wanted
+    // ones, so a short filter removes that spread (K_r = K/4 first); the
+    // slower near-window part (damped by theta_k / theta_i per pass) is small
+    // because the FP32 Lanczos ran to convergence at the rounding level.
+    // Rayleigh-Ritz on the filtered span removes the mixing among candidates.
+    // K_r = K/4, K/2, then K, at most 8 passes; target 5e-9 ||H|| (or tol if
+    // looser), under the 1e-8 ||H|| bar for returned residuals.
+    const double target = std::max(o.tol, 5e-9) * normH;
     const long long K_ref = K;
     long long K_r = std::max<long long>(16, K_ref / 4);
     (void)above;

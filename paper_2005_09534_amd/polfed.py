@@ -60,6 +60,14 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2005_09534_amd.build` "
                           "(or __graft_entry__.build())")
+    # The library must share torch's HIP runtime (torch brings its own copy;
+    # a second copy loaded first can fail to see the device): importing torch
+    # first makes the dynamic loader resolve the library's HIP dependency to
+    # the copy torch loaded.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "polfed_create": (c_int, [c_int, ctypes.POINTER(c_void_p)]),
@@ -87,7 +95,7 @@ def _load():
         "polfed_bounds": (c_int, [c_void_p, ctypes.POINTER(Model), c_int, c_ull, P_double,
                                   P_double, P_double, P_double]),
         "polfed_set_step_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int,
-                                          c_int]),
+                                          c_int, c_int]),
         "polfed_set_graphs": (c_int, [c_void_p, c_int]),
         "polfed_set_block_size": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
         "polfed_filter_stats": (c_int, [c_void_p, P_double, P_double, P_double, c_int]),
@@ -169,7 +177,8 @@ class Context:
         h = c_void_p()
         rc = LIB.polfed_create(device, ctypes.byref(h))
         if rc != OK:
-            raise PolfedError(rc, f"polfed_create({device}) failed (is a gfx950 GPU visible?)")
+            msg = LIB.polfed_last_error(None).decode(errors="replace")
+            raise PolfedError(rc, f"polfed_create({device}) failed: {msg}")
         self.h = h
         self.device = device
         self.bind_stream()
@@ -272,9 +281,9 @@ class Context:
         return tuple(o.value for o in out)
 
     # ---- tuning / measurement ----
-    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1):
+    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1, fused=0):
         self._check(LIB.polfed_set_step_shape(self.h, L, nvec, precision, threads, lpl, wg_per_cu,
-                                              lds_tables), "set_step_shape")
+                                              int(lds_tables), int(fused)), "set_step_shape")
 
     def set_block_size(self, L, precision, nev, block_size):
         self._check(LIB.polfed_set_block_size(self.h, L, precision, nev, block_size),

@@ -85,3 +85,16 @@ def test_create_without_device_fails_cleanly():
     h = ctypes.c_void_p()
     rc = pf.LIB.polfed_create(0, ctypes.byref(h))
     assert rc < 0 and not h.value
+    assert pf.LIB.polfed_last_error(None)  # the reason is reported without a context
+
+
+def test_one_hip_runtime_in_process():
+    """The binding loads the library after torch, so the process maps a single
+    HIP runtime (torch's); a second copy loaded first can fail to see the
+    device."""
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            if "libamdhip64" in line:
+                paths.add(line.split()[-1])
+    assert len(paths) == 1, paths

@@ -9,8 +9,9 @@ class _FakeCtx:
     def __init__(self):
         self.calls = []
 
-    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1):
-        self.calls.append(("shape", L, nvec, precision, threads, lpl, wg_per_cu, lds_tables))
+    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1, fused=0):
+        self.calls.append(("shape", L, nvec, precision, threads, lpl, wg_per_cu, lds_tables,
+                           fused))
 
     def set_block_size(self, L, precision, nev, block_size):
         self.calls.append(("block", L, precision, nev, block_size))
@@ -18,15 +19,15 @@ class _FakeCtx:
 
 def test_shape_candidates_are_valid():
     assert len(autotune.SHAPES) == len(set(autotune.SHAPES))
-    for t, lpl, wpc, lds in autotune.SHAPES:
-        assert t in (256, 1024) and lpl in (1, 2, 4) and lds in (0, 1)
+    for t, lpl, wpc, lds, fused in autotune.SHAPES:
+        assert t in (256, 1024) and lpl in (1, 2, 4) and lds in (0, 1) and fused in (0, 1)
         assert wpc >= 1
 
 
 def test_cache_round_trip_and_apply(tmp_path):
-    cache = {autotune._key("shape", 18, 0.0, 1, 32): [1024, 2, 2, 1, 2500.0],
+    cache = {autotune._key("shape", 18, 0.0, 1, 32): [1024, 2, 2, 1, 0, 2500.0],
              autotune._key("block", 18, 0.0, 1, 20): [8, 0.5],
-             autotune._key("shape", 22, 1.0, 0, 16): [256, 1, 8, 0, 1800.0]}
+             autotune._key("shape", 22, 1.0, 0, 16): [256, 1, 4, 0, 1, 1800.0]}
     path = tmp_path / "tune.json"
     autotune.save_cache(cache, str(path))
     assert json.loads(path.read_text()) == cache
@@ -34,9 +35,9 @@ def test_cache_round_trip_and_apply(tmp_path):
     assert back == cache
     ctx = _FakeCtx()
     autotune.apply_cache(ctx, back)
-    assert sorted(ctx.calls) == sorted([("shape", 18, 32, 1, 1024, 2, 2, 1),
+    assert sorted(ctx.calls) == sorted([("shape", 18, 32, 1, 1024, 2, 2, 1, 0),
                                         ("block", 18, 1, 20, 8),
-                                        ("shape", 22, 16, 0, 256, 1, 8, 0)])
+                                        ("shape", 22, 16, 0, 256, 1, 4, 0, 1)])
 
 
 def test_missing_cache_is_empty(tmp_path):

@@ -34,7 +34,9 @@ def test_shapes_bitwise_identical(ctx, precision, width):
     w = E1 - E0
     E0w, E1w = E0 - r0 - 1e-3 * w, E1 + r1 + 1e-3 * w
     ref = None
-    for sh in autotune.SHAPES[::3]:
+    fused = [sh for sh in autotune.SHAPES if sh[4] == 1]
+    assert fused
+    for sh in autotune.SHAPES[::3] + fused[::2]:
         ctx.set_step_shape(c.L, width, precision, *sh)
         Y = ctx.apply_filter(m, E0w, E1w, 0.0, 40, X)
         torch.cuda.synchronize()
@@ -61,3 +63,23 @@ def test_tune_shape_and_block(ctx):
     rb = ctx.solve_batch([m, m], 6, block_size=0, precision=0)
     assert [i["block_size"] for i in rb["info"]] == [best[0]] * 2
     np.testing.assert_array_equal(rb["E"][0], rb["E"][1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_shape_in_a_solve(ctx, precision):
+    """A solve whose filters run as one cooperative launch per block returns
+    the dense answer."""
+    from oracle import chain as ochain, dense
+    from paper_2005_09534_amd import polfed as pf
+    c = workloads.chain(12, 3.0, 1)
+    H = ochain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+    w = dense.full_spectrum(H)
+    normH = max(abs(w[0]), abs(w[-1]))
+    m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
+    ctx.set_step_shape(c.L, 4, precision, 256, 1, 2, 1, 1)
+    r = ctx.solve(m, 20, block_size=4, precision=precision, vectors=True)
+    assert r["status"] == pf.OK
+    Ed = w[dense.nearest_from_spectrum(w, r["info"]["sigma_energy"], 20)]
+    assert np.abs(r["E"] - Ed).max() <= 1e-10 * normH
+    res = np.linalg.norm(H @ r["V"] - r["V"] * r["E"], axis=0)
+    assert res.max() <= 1e-8 * normH
