@@ -79,15 +79,40 @@ def _cpu_baseline(wl, target_s=15.0, blocks=None):
                       f"block of the same chain (scipy CSR SpMM, 1 thread), {dt:.1f} s"}
 
 
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix
+
+
+def _gram_roofline(ctx, pf, n, p, q, reps=20):
+    """The Lanczos projection C = Q^T U (FP64 MFMA kernel k_gram + its
+    reduction) at the solve's final shape: n x p basis against an n x q
+    block.  HIP events on the stream the library runs on."""
+    import torch
+    Q = torch.randn((n, p), dtype=torch.float64, device="cuda")
+    U = torch.randn((n, q), dtype=torch.float64, device="cuda")
+    ctx.bind_stream()
+    ctx.gram(Q, U)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.gram(Q, U)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    flops = 2.0 * n * p * q
+    byts = 8.0 * n * (p + q)
+    return {"kernel": "k_gram (FP64 MFMA 16x16x4, Q^T U) + reduction", "n": n, "p": p, "q": q,
+            "us": 1e6 * s, "tflops": flops / s / 1e12,
+            "mfma_frac": flops / s / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+            "gbs": byts / s / 1e9, "hbm_frac": byts / s / 1e9 / HBM_PEAK_GBS,
+            "bound": "hbm" if flops / byts < FP64_MFMA_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS else "mfma"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3_fp64", "c3_fp32", "c4"])
-    ap.add_argument("--tune", action="store_true",
-                    help="autotune the step shape first (outside the timed region); workloads "
-                         "without a fixed block size always tune it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     args = ap.parse_args()
@@ -110,19 +135,25 @@ def main():
     opts = pf.default_opts(block_size=wl.block, K=wl.K, precision=prec, target_kind=0,
                            target=wl.eps_target)
     tune_s = 0.0
-    if args.tune or wl.block == 0:  # a workload without a fixed block size is autotuned
-        from paper_2005_09534_amd import autotune
+    from paper_2005_09534_amd import autotune
+    t0 = time.perf_counter()
+    if wl.block > 0:
+        # the step-kernel shape of this (L, width, precision), and of the FP32
+        # comparison solve, tuned outside the timed region
+        autotune.tune_shape(ctx, c, wl.block, prec)
+        if prec == 0 and not args.no_fp32:
+            autotune.tune_shape(ctx, c, wl.block, 1)
+    tune_s = time.perf_counter() - t0
+    if wl.block == 0:  # a workload without a fixed block size is autotuned
         t0 = time.perf_counter()
         by_L = {}
         for ch in wl.chains:
             by_L.setdefault(ch.L, []).append(ch)
         for L, chs in sorted(by_L.items()):
-            if wl.block == 0:
-                # a sample of this length (batch throughput when batched)
-                autotune.tune_block(ctx, chs[:8] if len(models) > 1 else chs[0], wl.nev, prec)
-            else:
-                autotune.tune_shape(ctx, chs[0], wl.block, prec)
-        tune_s = time.perf_counter() - t0
+            # a sample of this length (batch throughput when batched); tunes
+            # the step shape of every candidate width on the way
+            autotune.tune_block(ctx, chs[:8] if len(models) > 1 else chs[0], wl.nev, prec)
+        tune_s += time.perf_counter() - t0
 
     def step():
         if len(models) == 1:
@@ -205,6 +236,8 @@ def main():
             "max_resid_rel": i32["max_resid"] / i32["normH"], "refine_passes": i32["refine_passes"],
             "max_abs_eval_diff_vs_fp64": float(abs(r32["E"] - r["E"]).max()),
             "status": r32["status"]}
+    line["gram"] = _gram_roofline(ctx, pf, pf.dim(c.L), int(last["m"]) * int(last["block_size"]),
+                                  int(last["block_size"]))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = _cpu_baseline(wl, blocks=line["config"]["block"])
     ctx.close()

@@ -199,14 +199,12 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *model, int steps,
  * threads per workgroup (256 or 1024), 16-byte loads per lane per gathered
  * row (lpl: 1, 2 or 4), persistent workgroups per compute unit (1..32),
  * whether the rank tables are staged in LDS (ignored for L > 26), and
- * whether a whole filter application runs as one cooperative launch with a
- * grid-wide barrier between the K + 1 steps (fused != 0; the groups per CU
- * are then capped at what is co-resident, and a barrier wait over 2 s fails
- * the call with POLFED_EDEVICE) instead of one launch per step.  Entries live
- * in the context; without one the library's built-in default is used.  The
+ * whether the streamed operands are loaded before the neighbour gathers
+ * (early_loads != 0; results are identical either way).  Entries live in the
+ * context; without one the library's built-in default is used.  The
  * autotuner (paper_2005_09534_amd/autotune.py) searches this space. */
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads,
-                          int lpl, int wg_per_cu, int lds_tables, int fused);
+                          int lpl, int wg_per_cu, int lds_tables, int early_loads);
 /* Block size used when opts->block_size is 0 for chains of length L at the
  * given precision and N_ev (the autotuner's choice); without an entry a
  * built-in rule is used (about N_ev/4, capped at 16 in FP64 and 32 in FP32,

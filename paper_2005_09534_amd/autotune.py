@@ -3,8 +3,8 @@
 Two choices are tuned, both through the C ABI of libpolfed:
 
 * the launch shape of the fused Chebyshev-step kernel (threads per group,
-  16-byte loads per lane, persistent groups per CU, rank tables in LDS, one
-  launch per step or one cooperative launch for all steps) for a
+  16-byte loads per lane, persistent groups per CU, rank tables in LDS,
+  streamed loads before or after the neighbour gathers) for a
   (chain length L, block width, precision): each candidate applies the
   filter for a few dozen steps to a random block of the chain and is timed
   with the library's HIP-event counters; the fastest shape per HBM-second
@@ -24,11 +24,11 @@ import json
 import os
 import time
 
-# (threads, 16-byte loads per lane, groups per CU, LDS rank tables, fused
-# cooperative launch of all steps)
-SHAPES = [(t, lpl, wpc, lds, fused) for t, lpl, wpc, lds, fused in
+# (threads, 16-byte loads per lane, groups per CU, LDS rank tables, streamed
+# loads issued before the gathers)
+SHAPES = [(t, lpl, wpc, lds, early) for t, lpl, wpc, lds, early in
           itertools.product((256, 1024), (1, 2, 4), (1, 2, 4, 8, 16), (1, 0), (0, 1))
-          if not (t == 1024 and wpc > 2) and not (fused and (t == 1024 or wpc > 4))]
+          if not (t == 1024 and wpc > 2)]
 
 
 def cache_path():

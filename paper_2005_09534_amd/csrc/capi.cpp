@@ -137,10 +137,6 @@ int polfed_create(int device, polfed_ctx **out) {
     hipDeviceProp_t prop;
     PF_HIP(hipGetDeviceProperties(&prop, device));
     ctx->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    int wc_khz = 0;
-    if (hipDeviceGetAttribute(&wc_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess &&
-        wc_khz > 0)
-      ctx->wall_clock_hz = 1e3 * wc_khz;
     PF_HIP(hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
     ctx->stream = ctx->own_stream;
     ctx->use_graphs = std::getenv("POLFED_NO_GRAPH") ? 0 : 1;
@@ -339,7 +335,7 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *m, int steps, unsigned lo
 }
 
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads, int lpl,
-                          int wg_per_cu, int lds_tables, int fused) {
+                          int wg_per_cu, int lds_tables, int early_loads) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
     PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
@@ -352,7 +348,7 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
     sh.lpl = lpl;
     sh.wg_per_cu = wg_per_cu;
     sh.lds_tables = lds_tables ? 1 : 0;
-    sh.fused = fused ? 1 : 0;
+    sh.early_loads = early_loads ? 1 : 0;
     ctx->shapes[std::make_tuple(L, nvec, precision ? 4 : 8)] = sh;
     return POLFED_OK;
   });

@@ -89,7 +89,7 @@ struct Chunk {
 
 // One row of the fused step: out[r,:] for the lanes (col .. col+VEC) this
 // thread owns.  tA / tB are the rank tables (LDS or global).
-template <class T, int S, int LPL>
+template <class T, int S, int LPL, bool EARLY>
 __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int col,
                                          const int32_t *__restrict__ tA,
                                          const int32_t *__restrict__ tB) {
@@ -104,6 +104,16 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
   T acc[VEC];
 #pragma unroll
   for (int e = 0; e < VEC; ++e) acc[e] = T(0);
+  // EARLY: the streamed operands do not depend on the gathers; issuing their
+  // loads first overlaps their latency with the neighbour rounds (a gain
+  // where a step is one round of latency, small chains) at the cost of
+  // registers held across the gathers.  Either way they are added last, in
+  // the same order, so the result does not depend on EARLY.
+  T x[VEC], w[VEC];
+  if (EARLY) {
+    if (a.X != nullptr) load_row_nt<T, VEC, LDV>(a.X + (size_t)r * a.ldx + col, x);
+    if (a.W != nullptr) load_row_nt<T, VEC, LDV>(a.W + (size_t)r * a.ldw + col, w);
+  }
 
   if (a.V != nullptr) {
     const uint32_t s = a.states[r];
@@ -156,14 +166,12 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
   }
 
   if (a.X != nullptr) {
-    T x[VEC];
-    load_row_nt<T, VEC, LDV>(a.X + (size_t)r * a.ldx + col, x);
+    if (!EARLY) load_row_nt<T, VEC, LDV>(a.X + (size_t)r * a.ldx + col, x);
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] += a.alpha * x[e];
   }
   if (a.W != nullptr) {
-    T w[VEC];
-    load_row_nt<T, VEC, LDV>(a.W + (size_t)r * a.ldw + col, w);
+    if (!EARLY) load_row_nt<T, VEC, LDV>(a.W + (size_t)r * a.ldw + col, w);
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] += a.gamma * w[e];
   }
@@ -213,7 +221,7 @@ __device__ __forceinline__ void xcd_tiles(long long ntiles, long long &t_begin, 
   }
 }
 
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT>
+template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY>
 __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
   using C = StepCfg<T, S, LPL>;
   constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
@@ -232,7 +240,7 @@ __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
   for (long long t = t_begin; t < t_end; t += t_step) {
     const long long r = t * rows_per_iter + (long long)wave * RPW + slot;
     if (r >= a.n) continue;
-    step_row<T, S, LPL>(a, r, col, tA, tB);
+    step_row<T, S, LPL, EARLY>(a, r, col, tA, tB);
   }
 }
 
@@ -243,7 +251,7 @@ __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
 // end together; step Kmax is the final combination Y = (c_0 X + H~ b_1 -
 // b_2)/D.  Tiles run realisation-major, so an XCD works through whole
 // realisations.
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT>
+template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY>
 __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const BatchItem<T> *items,
                                                        int B, long long j, long long Kmax) {
   using C = StepCfg<T, S, LPL>;
@@ -296,177 +304,58 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
       a.w2 = (T)(0.5 * (double)it.w2 * it.Dinv);
       a.gamma = (T)(-it.Dinv);
     }
-    step_row<T, S, LPL>(a, r, col, tA, tB);
+    step_row<T, S, LPL, EARLY>(a, r, col, tA, tB);
   }
 }
 
-// Grid-wide barrier of a cooperative launch (every group resident).  Each
-// group arrives once per barrier on a counter that only grows; barrier number
-// `target / gridDim.x` is passed when the counter reaches `target`.  Every
-// wave waits for its own memory operations; then one thread releases the
-// group's stores at device scope (the L2s of the XCDs are not coherent with
-// each other), arrives, waits, and acquires for the group.
-// The wait is bounded by the device wall clock: a group that waits longer
-// than `timeout` ticks (or sees the flag set) sets sync[1] and returns false,
-// so every group leaves the kernel at its next barrier.
-__device__ __forceinline__ bool grid_barrier(unsigned *sync, unsigned target,
-                                             unsigned long long timeout) {
-  __shared__ int s_fail;
-  __builtin_amdgcn_s_waitcnt(0);  // this wave's loads and stores have completed
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    // one device-scope release (L2 write-back) per group, after every wave's
-    // stores have left it
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long t0 = wall_clock64();
-    int fail = 0;
-    while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
-          wall_clock64() - t0 > timeout) {
-        __hip_atomic_store(sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        fail = 1;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    s_fail = fail;
-    // one device-scope acquire per group: invalidates this CU's L1 and the
-    // XCD's L2 lines for every wave of the group
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-  return s_fail == 0;
-}
-
-// All K + 1 Clenshaw steps of one filter application in one launch (see
-// FusedArgs): step j < K computes b_k, k = K - j, into buffer j mod 3 from
-// b_{k+1} (buffer j-1) and b_{k+2} (buffer j-2); step K writes Y.  The rank
-// tables are staged once for all steps; each group keeps the same row tiles
-// in every step.
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_filter_fused(FusedArgs<T> f) {
-  using C = StepCfg<T, S, LPL>;
-  constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
-  extern __shared__ int32_t s_tab[];
-  const int32_t *tA, *tB;
-  stage_tables<LDS_TAB>(f.base.tabA, f.base.tabB, f.base.half, s_tab, tA, tB);
-
-  const long long n = f.base.n;
-  const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
-  const long long ntiles = (n + rows_per_iter - 1) / rows_per_iter;
-  long long t_begin, t_end, t_step;
-  xcd_tiles(ntiles, t_begin, t_end, t_step);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int slot = lane / G;
-  const int col = (lane % G) * VEC;
-  const size_t blk = (size_t)n * S;
-  T *bufs[3] = {f.buf, f.buf + blk, f.buf + 2 * blk};
-  const long long K = f.K;
-  for (long long j = 0; j <= K; ++j) {
-    StepArgs<T> a = f.base;
-    a.ldv = a.ldw = S;
-    if (j < K) {
-      const double ck = f.coef[K - j];
-      a.out = bufs[j % 3];
-      a.ldo = S;
-      a.V = (j >= 1) ? bufs[(j - 1) % 3] : nullptr;
-      a.W = (j >= 2) ? bufs[(j - 2) % 3] : nullptr;
-      a.X = (ck != 0.0) ? f.X : nullptr;
-      a.ldx = f.ldx;
-      a.alpha = (T)ck;
-      a.dscale = T(2);
-      a.w1 = (T)f.w1;
-      a.w2 = (T)f.w2;
-      a.gamma = T(-1);
-    } else {
-      a.out = f.Y;
-      a.ldo = f.ldy;
-      a.X = f.X;
-      a.ldx = f.ldx;
-      a.alpha = (T)(f.coef[0] * f.Dinv);
-      a.V = (K >= 1) ? bufs[(K - 1) % 3] : nullptr;
-      a.W = (K >= 2) ? bufs[(K - 2) % 3] : nullptr;
-      a.dscale = (T)f.Dinv;
-      a.w1 = (T)(0.5 * f.w1 * f.Dinv);
-      a.w2 = (T)(0.5 * f.w2 * f.Dinv);
-      a.gamma = (T)(-f.Dinv);
-    }
-    for (long long t = t_begin; t < t_end; t += t_step) {
-      const long long r = t * rows_per_iter + (long long)wave * RPW + slot;
-      if (r < n) step_row<T, S, LPL>(a, r, col, tA, tB);
-    }
-    if (j < K && !grid_barrier(f.sync, (unsigned)((j + 1) * gridDim.x), f.timeout_ticks)) return;
-  }
-}
-
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT>
-static bool launch_fused_k(hipStream_t st, const FusedArgs<T> &f, const StepShape &shape,
-                           int num_cu, size_t shm) {
-  using C = StepCfg<T, S, LPL>;
-  auto kern = k_filter_fused<T, S, LPL, LDS_TAB, MAXT>;
-  int per_cu = 0;
-  PF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, MAXT, shm));
-  const long long rows_per_iter = (long long)(MAXT / 64) * C::RPW;
-  const long long tiles = (f.base.n + rows_per_iter - 1) / rows_per_iter;
-  long long nwg = (long long)num_cu * std::min(per_cu, shape.wg_per_cu);
-  nwg = std::min(nwg, ((tiles + 7) / 8) * 8);
-  nwg = (nwg / 8) * 8;  // the per-XCD tile schedule wants a multiple of 8
-  if (nwg < 8 || (double)(f.K + 1) * (double)nwg >= 4.0e9) return false;
-  FusedArgs<T> arg = f;
-  void *params[] = {&arg};
-  PF_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3((unsigned)nwg),
-                                    dim3(MAXT), params, (unsigned)shm, st));
-  check_launch("k_filter_fused");
-  return true;
-}
-
-// The fused kernel keeps its per-step state in registers; it is built for
-// 256-thread groups only (1024-thread groups would spill), a 1024-thread
-// shape running as four times as many 256-thread groups.
-template <class T, int S, int LPL>
-static bool launch_fused_s(hipStream_t st, const FusedArgs<T> &f, const StepShape &shape,
-                           int num_cu) {
-  const bool lds = shape.lds_tables && f.base.L <= kMaxLdsTableL;
-  const size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << f.base.half) : 0;
-  if (shape.threads != 256 && shape.threads != 1024)
+// Calls f.template operator()<LDS_TAB, MAXT, EARLY>() for the runtime choice.
+template <class F>
+static void dispatch_shape(bool lds, int threads, bool early, F &&f) {
+  if (threads != 256 && threads != 1024)
     throw Error(POLFED_EINVAL, "step kernel: threads must be 256 or 1024");
-  StepShape sh = shape;
-  if (sh.threads == 1024) {
-    sh.threads = 256;
-    sh.wg_per_cu *= 4;
+  if (threads == 1024) {
+    if (lds)
+      early ? f.template operator()<true, 1024, true>() : f.template operator()<true, 1024, false>();
+    else
+      early ? f.template operator()<false, 1024, true>() : f.template operator()<false, 1024, false>();
+  } else {
+    if (lds)
+      early ? f.template operator()<true, 256, true>() : f.template operator()<true, 256, false>();
+    else
+      early ? f.template operator()<false, 256, true>() : f.template operator()<false, 256, false>();
   }
-  return lds ? launch_fused_k<T, S, LPL, true, 256>(st, f, sh, num_cu, shm)
-             : launch_fused_k<T, S, LPL, false, 256>(st, f, sh, num_cu, 0);
 }
 
-template <class T>
-bool launch_filter_fused(hipStream_t st, int S, const FusedArgs<T> &f, const StepShape &shape,
-                         int num_cu) {
-  if (f.base.n <= 0) return true;
-#define PF_FUSED_CASE(SS)                                                   \
-  case SS:                                                                  \
-    if (shape.lpl == 2) return launch_fused_s<T, SS, 2>(st, f, shape, num_cu); \
-    if (shape.lpl == 4) return launch_fused_s<T, SS, 4>(st, f, shape, num_cu); \
-    return launch_fused_s<T, SS, 1>(st, f, shape, num_cu);
-  switch (S) {
-    PF_FUSED_CASE(1)
-    PF_FUSED_CASE(2)
-    PF_FUSED_CASE(4)
-    PF_FUSED_CASE(8)
-    PF_FUSED_CASE(16)
-    PF_FUSED_CASE(32)
-    PF_FUSED_CASE(64)
-    default: throw Error(POLFED_EINVAL, "block width must be a power of two in [1, 64]");
+// Launchers of the two step kernels for one (T, S, LPL), called by
+// dispatch_shape with the remaining template parameters.
+template <class T, int S, int LPL>
+struct StepLaunch {
+  hipStream_t st;
+  const StepArgs<T> &a;
+  long long nwg;
+  int threads;
+  size_t shm;
+  template <bool LDS_TAB, int MAXT, bool EARLY>
+  void operator()() const {
+    k_step<T, S, LPL, LDS_TAB, MAXT, EARLY><<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a);
   }
-#undef PF_FUSED_CASE
-}
+};
 
-template bool launch_filter_fused<float>(hipStream_t, int, const FusedArgs<float> &,
-                                         const StepShape &, int);
-template bool launch_filter_fused<double>(hipStream_t, int, const FusedArgs<double> &,
-                                          const StepShape &, int);
+template <class T, int S, int LPL>
+struct BatchedLaunch {
+  hipStream_t st;
+  const StepArgs<T> &a;
+  const BatchItem<T> *items;
+  int B;
+  long long j, Kmax, nwg;
+  int threads;
+  size_t shm;
+  template <bool LDS_TAB, int MAXT, bool EARLY>
+  void operator()() const {
+    k_step_batched<T, S, LPL, LDS_TAB, MAXT, EARLY>
+        <<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a, items, B, j, Kmax);
+  }
+};
 
 template <class T, int S, int LPL>
 static void launch_step_s(hipStream_t st, const StepArgs<T> &a0, const StepShape &shape,
@@ -483,20 +372,9 @@ static void launch_step_s(hipStream_t st, const StepArgs<T> &a0, const StepShape
   nwg = ((nwg + 7) / 8) * 8;
   a.rows_per_wg = rows_per_iter;
   const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
-  size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
-  if (threads > 256) {
-    if (threads != 1024) throw Error(POLFED_EINVAL, "step kernel: threads must be 256 or 1024");
-    if (lds)
-      k_step<T, S, LPL, true, 1024><<<(unsigned)nwg, threads, shm, st>>>(a);
-    else
-      k_step<T, S, LPL, false, 1024><<<(unsigned)nwg, threads, 0, st>>>(a);
-  } else {
-    if (threads != 256) throw Error(POLFED_EINVAL, "step kernel: threads must be 256 or 1024");
-    if (lds)
-      k_step<T, S, LPL, true, 256><<<(unsigned)nwg, threads, shm, st>>>(a);
-    else
-      k_step<T, S, LPL, false, 256><<<(unsigned)nwg, threads, 0, st>>>(a);
-  }
+  const size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
+  dispatch_shape(lds, threads, shape.early_loads != 0,
+                 StepLaunch<T, S, LPL>{st, a, nwg, threads, shm});
   check_launch("k_step");
 }
 
@@ -511,18 +389,9 @@ static void launch_batched_s(hipStream_t st, const StepArgs<T> &a, const BatchIt
   long long nwg = std::min((long long)num_cu * shape.wg_per_cu, tiles);
   nwg = ((nwg + 7) / 8) * 8;
   const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
-  size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
-  if (threads > 256) {
-    if (lds)
-      k_step_batched<T, S, LPL, true, 1024><<<(unsigned)nwg, threads, shm, st>>>(a, items, B, j, Kmax);
-    else
-      k_step_batched<T, S, LPL, false, 1024><<<(unsigned)nwg, threads, 0, st>>>(a, items, B, j, Kmax);
-  } else {
-    if (lds)
-      k_step_batched<T, S, LPL, true, 256><<<(unsigned)nwg, threads, shm, st>>>(a, items, B, j, Kmax);
-    else
-      k_step_batched<T, S, LPL, false, 256><<<(unsigned)nwg, threads, 0, st>>>(a, items, B, j, Kmax);
-  }
+  const size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
+  dispatch_shape(lds, threads, shape.early_loads != 0,
+                 BatchedLaunch<T, S, LPL>{st, a, items, B, j, Kmax, nwg, threads, shm});
   check_launch("k_step_batched");
 }
 

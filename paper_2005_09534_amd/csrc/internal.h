@@ -124,7 +124,7 @@ struct StepShape {
   int lpl = 1;           // 16-byte loads per lane per gathered row
   int wg_per_cu = 8;     // persistent workgroups per CU
   int lds_tables = 1;    // stage rank tables in LDS
-  int fused = 0;         // all K+1 steps in one cooperative launch
+  int early_loads = 0;   // issue the streamed loads before the gathers
 };
 
 template <class T>
@@ -147,33 +147,6 @@ struct BatchItem {
 template <class T>
 void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const BatchItem<T> *items,
                          int B, long long j, long long Kmax, const StepShape &shape, int num_cu);
-// A whole filter application Y = P^K(H~) X in one cooperative launch: the
-// K + 1 Clenshaw steps of k_step run back to back, separated by a grid-wide
-// barrier on `sync` (two zeroed words: arrival counter, error flag).  A
-// barrier wait longer than timeout_ticks of the device wall clock sets the
-// error flag and ends the kernel.
-template <class T>
-struct FusedArgs {
-  StepArgs<T> base;       // chain, basis, tables, dt
-  const T *X;
-  long long ldx;
-  T *Y;
-  long long ldy;
-  T *buf;                 // 3 recurrence blocks of n x S (ld S)
-  const double *coef;     // c_0 .. c_K (device)
-  long long K;
-  double Dinv;            // 1 / D
-  double w1, w2;          // a J1, a J2
-  unsigned *sync;         // [0] arrivals, [1] error flag
-  unsigned long long timeout_ticks;
-};
-
-// Returns false (launching nothing) when the shape cannot be made
-// co-resident on the device.
-template <class T>
-bool launch_filter_fused(hipStream_t st, int S, const FusedArgs<T> &f, const StepShape &shape,
-                         int num_cu);
-
 // Built-in default shape (used when the context holds no tuned entry).
 StepShape default_shape(int L, int S, bool fp32);
 
@@ -279,8 +252,6 @@ struct polfed_ctx {
   hipGraphExec_t filter_graph = nullptr;
   std::vector<unsigned long long> filter_graph_key;
   int use_graphs = 1;
-  // device wall-clock ticks per second (bounded barrier waits)
-  double wall_clock_hz = 1e8;
   polfed::DevBuf &buf(const std::string &name) {
     auto &p = bufs[name];
     if (!p) p.reset(new polfed::DevBuf());

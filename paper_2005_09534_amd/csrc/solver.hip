@@ -136,7 +136,7 @@ static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shap
   st.ldo = ldy;
   st.X = X;
   st.ldx = ldx;
-  // (same rounding as the fused kernel: products with 1/D)
+  // (products with 1/D, as in the batched kernel)
   const double Dinv = 1.0 / D;
   st.alpha = (T)(coef[0] * Dinv);
   if (K >= 1) {
@@ -187,46 +187,6 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
                        (K >= 1 ? 4.0 + sizeof(T) : 0.0));
     return mv;
   };
-  if (shape.fused && K >= 1) {
-    // one cooperative launch for all K + 1 steps
-    double *coefd = static_cast<double *>(ctx->buf("fused_coef").ensure(sizeof(double) * (K + 1)));
-    unsigned *sync = static_cast<unsigned *>(ctx->buf("fused_sync").ensure(64));
-    PF_HIP(hipMemcpyAsync(coefd, coef.data(), sizeof(double) * (K + 1), hipMemcpyHostToDevice,
-                          ctx->stream));
-    launch_fill(ctx->stream, reinterpret_cast<double *>(sync), 1, 0.0);
-    FusedArgs<T> f;
-    f.base = base_args<T>(c, dt);
-    f.X = X;
-    f.ldx = ldx;
-    f.Y = Y;
-    f.ldy = ldy;
-    f.buf = buf3;
-    f.coef = coefd;
-    f.K = K;
-    f.Dinv = 1.0 / D;
-    f.w1 = a * c.J1;
-    f.w2 = a * c.J2;
-    f.sync = sync;
-    f.timeout_ticks = (unsigned long long)(2.0 * ctx->wall_clock_hz);  // 2 s per barrier
-    PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
-    if (launch_filter_fused<T>(ctx->stream, S, f, shape, ctx->num_cu)) {
-      moved = step_bytes();
-      if (bytes) *bytes += moved;
-      PF_HIP(hipEventRecord(ctx->ev_stop, ctx->stream));
-      PF_HIP(hipEventSynchronize(ctx->ev_stop));
-      unsigned flag[2] = {0u, 0u};
-      PF_HIP(hipMemcpy(flag, sync, sizeof(flag), hipMemcpyDeviceToHost));
-      if (flag[1] != 0u)
-        throw Error(POLFED_EDEVICE, "fused filter: a grid barrier timed out");
-      float ms = 0.0f;
-      PF_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
-      ctx->filter_gpu_s += 1e-3 * ms;
-      ctx->filter_launches += (double)(K + 1);
-      ctx->filter_bytes += moved;
-      return;
-    }
-    // not co-resident with this shape: the step-per-launch path below
-  }
   if (ctx->use_graphs && graph_worthwhile<T>(n, S, K)) {
     // key: every value baked into the launches
     std::vector<unsigned long long> key = {
@@ -236,7 +196,8 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
         (unsigned long long)(uintptr_t)dt, (unsigned long long)(uintptr_t)buf3,
         (unsigned long long)(uintptr_t)c.basis->states.p,
         (unsigned long long)shape.threads, (unsigned long long)shape.lpl,
-        (unsigned long long)shape.wg_per_cu, (unsigned long long)shape.lds_tables};
+        (unsigned long long)shape.wg_per_cu, (unsigned long long)shape.lds_tables,
+        (unsigned long long)shape.early_loads};
     auto bits = [](double v) {
       unsigned long long u;
       std::memcpy(&u, &v, sizeof(u));
@@ -1227,10 +1188,14 @@ template void stage_apply_filter<double>(polfed_ctx *, const Chain &, double, do
 // ----------------------------------------------------------- tuning --
 
 StepShape default_shape(int L, int S, bool fp32) {
-  // From a sweep of (threads, loads per lane, groups per CU, LDS tables) on
-  // gfx950: two 16-byte loads per lane win for every L; large chains
-  // (L >= 22, 16-64 KB of rank tables per group) prefer two 1024-thread
-  // groups per CU, mid-size ones sixteen 256-thread groups.
+  // From sweeps of (threads, loads per lane, groups per CU, LDS tables,
+  // early streamed loads) on gfx950 boxes: two 16-byte loads per lane are
+  // never worse than one by more than a few per cent and one load per lane
+  // was 2x slower on some boxes at L >= 18; chains up to L = 20 prefer
+  // sixteen 256-thread groups per CU with the rank tables read through the
+  // caches, and up to L = 18 (a step is about one round of memory latency)
+  // early streamed loads; L >= 22 prefers two 1024-thread groups per CU with
+  // the tables in LDS.  Short chains (L <= 16) sit at the launch floor.
   StepShape sh;
   sh.lds_tables = 1;
   sh.lpl = 2;
@@ -1238,18 +1203,18 @@ StepShape default_shape(int L, int S, bool fp32) {
     sh.threads = 256;
     sh.wg_per_cu = 8;
     sh.lpl = 1;
-  } else if (L == 18) {
-    sh.threads = 1024;
-    sh.wg_per_cu = 2;
+    sh.lds_tables = 0;
   } else if (L <= 20) {
     sh.threads = 256;
     sh.wg_per_cu = 16;
+    sh.lds_tables = 0;
+    sh.early_loads = (L <= 18) ? 1 : 0;
   } else {
     sh.threads = 1024;
     sh.wg_per_cu = 2;
-    if (L == 24 || (L == 22 && fp32)) sh.lpl = 1;
   }
   (void)S;
+  (void)fp32;
   return sh;
 }
 

@@ -281,9 +281,11 @@ class Context:
         return tuple(o.value for o in out)
 
     # ---- tuning / measurement ----
-    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1, fused=0):
+    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1,
+                       early_loads=0):
         self._check(LIB.polfed_set_step_shape(self.h, L, nvec, precision, threads, lpl, wg_per_cu,
-                                              int(lds_tables), int(fused)), "set_step_shape")
+                                              int(lds_tables), int(early_loads)),
+                    "set_step_shape")
 
     def set_block_size(self, L, precision, nev, block_size):
         self._check(LIB.polfed_set_block_size(self.h, L, precision, nev, block_size),

@@ -9,9 +9,9 @@ class _FakeCtx:
     def __init__(self):
         self.calls = []
 
-    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1, fused=0):
+    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1, early_loads=0):
         self.calls.append(("shape", L, nvec, precision, threads, lpl, wg_per_cu, lds_tables,
-                           fused))
+                           early_loads))
 
     def set_block_size(self, L, precision, nev, block_size):
         self.calls.append(("block", L, precision, nev, block_size))
@@ -19,8 +19,8 @@ class _FakeCtx:
 
 def test_shape_candidates_are_valid():
     assert len(autotune.SHAPES) == len(set(autotune.SHAPES))
-    for t, lpl, wpc, lds, fused in autotune.SHAPES:
-        assert t in (256, 1024) and lpl in (1, 2, 4) and lds in (0, 1) and fused in (0, 1)
+    for t, lpl, wpc, lds, early in autotune.SHAPES:
+        assert t in (256, 1024) and lpl in (1, 2, 4) and lds in (0, 1) and early in (0, 1)
         assert wpc >= 1
 
 

@@ -34,9 +34,9 @@ def test_shapes_bitwise_identical(ctx, precision, width):
     w = E1 - E0
     E0w, E1w = E0 - r0 - 1e-3 * w, E1 + r1 + 1e-3 * w
     ref = None
-    fused = [sh for sh in autotune.SHAPES if sh[4] == 1]
-    assert fused
-    for sh in autotune.SHAPES[::3] + fused[::2]:
+    early = [sh for sh in autotune.SHAPES if sh[4] == 1]
+    assert early
+    for sh in autotune.SHAPES[::3] + early[::2]:
         ctx.set_step_shape(c.L, width, precision, *sh)
         Y = ctx.apply_filter(m, E0w, E1w, 0.0, 40, X)
         torch.cuda.synchronize()
@@ -66,9 +66,9 @@ def test_tune_shape_and_block(ctx):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_fused_shape_in_a_solve(ctx, precision):
-    """A solve whose filters run as one cooperative launch per block returns
-    the dense answer."""
+def test_early_loads_shape_in_a_solve(ctx, precision):
+    """A solve whose step kernel issues the streamed loads before the gathers
+    returns the dense answer."""
     from oracle import chain as ochain, dense
     from paper_2005_09534_amd import polfed as pf
     c = workloads.chain(12, 3.0, 1)
