@@ -92,7 +92,8 @@ typedef struct {
   int nev_window;         /* eigenvalues the window was sized for           */
   int block_size;         /* s used                                         */
   int m;                  /* Lanczos blocks at stop                         */
-  int n_conv;             /* pairs with residual <= tol ||H||              */
+  int n_conv;             /* pairs with residual <= tol ||H|| (FP32 mode:
+                             max(tol, 1e-8) ||H||)                          */
   int refine_passes;      /* FP64 refinement passes (precision 1); -1 when
                              the FP32 result missed 1e-8 ||H|| and was
                              recomputed with the FP64 filter               */

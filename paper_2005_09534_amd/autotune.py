@@ -103,7 +103,7 @@ def tune_block(ctx, chains, nev, precision, widths=(4, 8, 16, 32), cache=None, s
     models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in chains]
     best = None
     for s in widths:
-        if s > nev * 2:
+        if s > nev:  # wider blocks than N_ev waste columns and can hit the column cap
             continue
         tune_shape(ctx, chains[0], s, precision, cache=shape_cache)
 

@@ -370,6 +370,13 @@ static polfed_opts resolve_opts(const polfed_opts *in) {
 // filter_X() / [the filter, alone or batched] / lanczos_step() until done,
 // then finalize().  Device state that must live across Lanczos steps is
 // owned here; scratch that is consumed within one step is the context's.
+// Residual bar of returned pairs in FP32-filter mode: a result whose FP64
+// refinement could not bring every residual to 1e-8 ||H|| (this happens when
+// the Gaussian density of states overestimated the window, so that wanted
+// values sit below p where the filter separates them poorly) is recomputed
+// with the FP64 filter; info->refine_passes is then -1.
+constexpr double kFp32ResidBar = 1e-8;
+
 template <class T>
 struct Realization {
   polfed_ctx *ctx = nullptr;
@@ -640,6 +647,9 @@ void Realization<T>::lanczos_step() {
     t_eig += now_s() - t2;
   }
   if (nconv >= nev || m_done >= m_max) done = true;
+  if (std::getenv("POLFED_VERBOSE"))
+    fprintf(stderr, "[polfed] L=%d block %d/%d: %d of %d converged (filter %.2f s so far)\n", c.L,
+            m_done, m_max, nconv, nev, t_filter);
 }
 
 template <class T>
@@ -742,13 +752,16 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
     }
     const int nc = (int)cand.size();
     // refined columns (FP32 mode): all candidates, so that every in-window
-    // error direction lies in the Rayleigh-Ritz space; padded to whole
-    // kernel widths (a power of two up to 64, then multiples of 64) so that a
-    // short, launch-bound step moves as many columns as possible
+    // error direction lies in the Rayleigh-Ritz space; padded to kernel
+    // widths: whole 64-column launches, then the remainder rounded up to a
+    // power of two
     const int q = nc;
-    int qpad = 1;
-    while (qpad < q && qpad < 64) qpad *= 2;
-    if (q > 64) qpad = ((q + 63) / 64) * 64;
+    int qpad = 64 * (q / 64);
+    if (q % 64) {
+      int w = 1;
+      while (w < q % 64) w *= 2;
+      qpad += w;
+    }
     const int ldr = std::max(((nc + 7) / 8) * 8, qpad);
     PF_HIP(hipMemcpyAsync(didx, cand.data(), sizeof(int) * nc, hipMemcpyHostToDevice, st));
     double *Tsel = static_cast<double *>(ctx->buf("Tsel").ensure(sizeof(double) * (size_t)ms * ldr));
@@ -822,7 +835,7 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
       launch_gather_cols(st, n, q, WR, ldr, didx, Vn, ldr);
       cheb_coeffs(sigma, K_r, coef_r, D_r);
       for (int c0 = 0; c0 < qpad; c0 += 64) {
-        const int w = std::min(64, qpad - c0);
+        const int w = std::min(64, qpad - c0);  // 64, or the power-of-two remainder
         run_filter<double>(ctx, c, dt64, a, w, Vn + c0, ldr, UR + c0, ldr, K_r, coef_r, D_r, cheb64,
                            false, &refine_bytes);
       }
@@ -879,7 +892,8 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
   int n_ok = 0;
   double rmax = 0.0;
   for (int i = 0; i < nout; ++i) {
-    if (r[i] <= o.tol * normH) ++n_ok;
+    // FP32 mode is held to the FP32 residual bar (its refinement target)
+    if (r[i] <= (fp32 ? std::max(o.tol, kFp32ResidBar) : o.tol) * normH) ++n_ok;
     rmax = std::max(rmax, r[i]);
   }
   inf.E0 = E0;
@@ -933,12 +947,6 @@ static int solve_single(polfed_ctx *ctx, const polfed_model *model, const polfed
   return R.finalize(evals, evecs, resid, info);
 }
 
-// Residual bar of returned pairs in FP32-filter mode: a result whose FP64
-// refinement could not bring every residual to 1e-8 ||H|| (this happens when
-// the Gaussian density of states overestimated the window, so that wanted
-// values sit below p where the filter separates them poorly) is recomputed
-// with the FP64 filter; info->refine_passes is then -1.
-constexpr double kFp32ResidBar = 1e-8;
 
 static int fp64_resolve(polfed_ctx *ctx, const polfed_model *model, const polfed_opts &o, int nev,
                         double *evals, double *evecs, double *resid, polfed_info *info,
