@@ -37,21 +37,64 @@ def _kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(workload):
+def _traffic(workload, shape):
     """HBM bytes per step launch from committed rocprofv3 --pmc summaries
     (FETCH_SIZE / WRITE_SIZE, scaled by the copy-kernel calibration), or
-    None when absent or taken on a different kernel source."""
+    None when absent, taken on a different kernel source or launch shape."""
     path = os.path.join(ROOT, "profiles", f"k_step_{workload}_traffic.txt")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or shape is None:
         return None
     txt = open(path).read()
     kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)\s*$", txt, flags=re.M))
     if kv.get("kernel_source_sha256_16") != _kernel_hash():
         return None
+    if kv.get("step_shape") != ",".join(str(int(v)) for v in shape):
+        return None
     try:
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _fp64_single_estimate(ctx, pf, wl, batch_s):
+    """The plain FP64 path on the same realisations, one polfed_solve each:
+    one realisation per (L, W) cell is solved and timed, and the time is
+    scaled by the cell's size.  Compared with the batched FP32 solve."""
+    import torch
+    cells = {}
+    for ch in wl.chains:
+        cells.setdefault((ch.L, ch.W), []).append(ch)
+    total, sample = 0.0, 0
+    for (L, W), chs in sorted(cells.items()):
+        ch = chs[0]
+        m = pf.make_model(ch.L, ch.J1, ch.J2, ch.Delta, ch.h)
+        o = pf.default_opts(block_size=0, precision=0, target_kind=0, target=wl.eps_target)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.solve(m, wl.nev, opts=o, vectors=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if r["status"] != pf.OK:
+            print(f"warning: FP64 single solve of L={L} W={W} returned {r['status']}",
+                  file=sys.stderr)
+        total += dt * len(chs)
+        sample += 1
+    return {"time_s_estimate": total, "realisations": len(wl.chains), "sampled": sample,
+            "sample": "one realisation per (L, W) cell, solved alone in FP64 (default block "
+                      "size), time scaled by the cell's size",
+            "batched_fp32_speedup": total / batch_s}
+
+
+def _profiled_shape(workload):
+    """Step shape recorded with the committed traffic counters, if they were
+    taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)\s*$", open(path).read(), flags=re.M))
+    if kv.get("kernel_source_sha256_16") != _kernel_hash() or "step_shape" not in kv:
+        return None
+    return [int(v) for v in kv["step_shape"].split(",")]
 
 
 def _cpu_baseline(wl, target_s=15.0, blocks=None):
@@ -113,6 +156,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3_fp64", "c3_fp32", "c4"])
+    ap.add_argument("--shape", default="",
+                    help="step shape threads,lpl,wg_per_cu,lds_tables,early_loads (else the "
+                         "profiled one, else tuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     args = ap.parse_args()
@@ -138,9 +184,17 @@ def main():
     from paper_2005_09534_amd import autotune
     t0 = time.perf_counter()
     if wl.block > 0:
-        # the step-kernel shape of this (L, width, precision), and of the FP32
-        # comparison solve, tuned outside the timed region
-        autotune.tune_shape(ctx, c, wl.block, prec)
+        # the step-kernel shape of this (L, width, precision): the one the
+        # committed rocprofv3 counters were taken on (when they match this
+        # kernel source), else tuned; the FP32 comparison solve's shape is
+        # tuned.  All outside the timed region.
+        prof = _profiled_shape(args.workload)
+        if args.shape:
+            ctx.set_step_shape(c.L, wl.block, prec, *[int(v) for v in args.shape.split(",")])
+        elif prof is not None:
+            ctx.set_step_shape(c.L, wl.block, prec, *prof)
+        else:
+            autotune.tune_shape(ctx, c, wl.block, prec)
         if prec == 0 and not args.no_fp32:
             autotune.tune_shape(ctx, c, wl.block, 1)
     tune_s = time.perf_counter() - t0
@@ -202,7 +256,9 @@ def main():
                    "nev": wl.nev, "block": sorted(set(i["block_size"] for i in infos)),
                    "K": last["K"] if len(models) == 1 else [min(i["K"] for i in infos), max(i["K"] for i in infos)],
                    "lanczos_blocks": last["m"] if len(models) == 1 else [min(i["m"] for i in infos), max(i["m"] for i in infos)],
-                   "precision": wl.precision, "autotune_s": tune_s},
+                   "precision": wl.precision, "autotune_s": tune_s,
+                   "step_shape": (list(ctx.get_step_shape(c.L, wl.block, prec))
+                                  if wl.block > 0 else None)},
         "time_to_nev_s": wall / args.steps,
         "solve": {k: last[k] for k in ("t_bounds", "t_filter", "t_orth", "t_eig", "t_rr",
                                        "t_refine", "t_total", "max_resid", "normH", "n_conv",
@@ -215,7 +271,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": _traffic(args.workload),
+            "traffic": _traffic(args.workload, ctx.get_step_shape(c.L, wl.block, prec)
+                                if wl.block > 0 else None),
             "avg_launch_us": 1e6 * fgpu / flaunch if flaunch else None,
             "algorithmic_bytes_per_launch": fbytes / flaunch if flaunch else None,
             "launches": flaunch,
@@ -238,6 +295,8 @@ def main():
             "status": r32["status"]}
     line["gram"] = _gram_roofline(ctx, pf, pf.dim(c.L), int(last["m"]) * int(last["block_size"]),
                                   int(last["block_size"]))
+    if len(models) > 1 and not args.no_fp32:
+        line["fp64_single"] = _fp64_single_estimate(ctx, pf, wl, wall / args.steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = _cpu_baseline(wl, blocks=line["config"]["block"])
     ctx.close()

@@ -206,6 +206,10 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *model, int steps,
  * autotuner (paper_2005_09534_amd/autotune.py) searches this space. */
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads,
                           int lpl, int wg_per_cu, int lds_tables, int early_loads);
+/* The step shape in force for (L, nvec, precision): the context's entry,
+ * else the built-in default.  Outputs as in polfed_set_step_shape. */
+int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads,
+                          int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads);
 /* Block size used when opts->block_size is 0 for chains of length L at the
  * given precision and N_ev (the autotuner's choice); without an entry a
  * built-in rule is used (about N_ev/4, capped at 16 in FP64 and 32 in FP32,

@@ -55,9 +55,13 @@ def _key(kind, L, J2, precision, x):
     return f"{kind}:{L}:{int(J2 != 0.0)}:{precision}:{x}"
 
 
-def tune_shape(ctx, chain, width, precision, steps=None, shapes=SHAPES, cache=None):
+def tune_shape(ctx, chain, width, precision, steps=None, shapes=SHAPES, cache=None, margin=0.03):
     """Fastest step-kernel shape for the chain's L at this width/precision.
-    Leaves it set on ctx; returns (shape, GB/s)."""
+
+    The shape in force (the library default, or an earlier choice) is kept
+    unless another is faster by more than `margin`, so that near-ties do not
+    flip the choice from run to run.  Leaves the choice set on ctx; returns
+    (shape, GB/s)."""
     import torch
     from . import polfed as pf
     m = pf.make_model(chain.L, chain.J1, chain.J2, chain.Delta, chain.h)
@@ -68,20 +72,26 @@ def tune_shape(ctx, chain, width, precision, steps=None, shapes=SHAPES, cache=No
     if steps is None:
         steps = max(8, min(200, int(2e9 / (n * width * (4 if precision else 8) * 4))))
     E0, E1 = -2.0 * chain.L, 2.0 * chain.L  # any enclosing interval; cost is independent of it
-    best = None
-    for sh in shapes:
+
+    def rate(sh):
         ctx.set_step_shape(chain.L, width, precision, *sh)
         ctx.apply_filter(m, E0, E1, 0.0, 2, X, out=Y)
         ctx.filter_stats(reset=True)
         ctx.apply_filter(m, E0, E1, 0.0, steps, X, out=Y)
         st = ctx.filter_stats(reset=True)
-        gbs = st["bytes"] / st["gpu_s"] / 1e9
-        if best is None or gbs > best[1]:
-            best = (sh, gbs)
+        return st["bytes"] / st["gpu_s"] / 1e9
+
+    current = tuple(ctx.get_step_shape(chain.L, width, precision))
+    best = (current, rate(current))
+    for sh in shapes:
+        if tuple(sh) == current:
+            continue
+        gbs = rate(sh)
+        if gbs > best[1] * (1.0 + margin if best[0] == current else 1.0):
+            best = (tuple(sh), gbs)
     ctx.set_step_shape(chain.L, width, precision, *best[0])
     if cache is not None:
         cache[_key("shape", chain.L, chain.J2, precision, width)] = list(best[0]) + [best[1]]
-
     return best
 
 

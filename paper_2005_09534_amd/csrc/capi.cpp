@@ -354,6 +354,24 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
   });
 }
 
+int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads, int *lpl,
+                          int *wg_per_cu, int *lds_tables, int *early_loads) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
+    PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
+    PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
+    PF_REQUIRE(threads && lpl && wg_per_cu && lds_tables && early_loads, "NULL output");
+    auto it = ctx->shapes.find(std::make_tuple(L, nvec, precision ? 4 : 8));
+    const StepShape sh = (it != ctx->shapes.end()) ? it->second : default_shape(L, nvec, precision != 0);
+    *threads = sh.threads;
+    *lpl = sh.lpl;
+    *wg_per_cu = sh.wg_per_cu;
+    *lds_tables = sh.lds_tables;
+    *early_loads = sh.early_loads;
+    return POLFED_OK;
+  });
+}
+
 int polfed_set_block_size(polfed_ctx *ctx, int L, int precision, int nev, int block_size) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");

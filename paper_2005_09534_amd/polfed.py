@@ -96,6 +96,7 @@ def _load():
                                   P_double, P_double, P_double]),
         "polfed_set_step_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int,
                                           c_int, c_int]),
+        "polfed_get_step_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 5),
         "polfed_set_graphs": (c_int, [c_void_p, c_int]),
         "polfed_set_block_size": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
         "polfed_filter_stats": (c_int, [c_void_p, P_double, P_double, P_double, c_int]),
@@ -286,6 +287,12 @@ class Context:
         self._check(LIB.polfed_set_step_shape(self.h, L, nvec, precision, threads, lpl, wg_per_cu,
                                               int(lds_tables), int(early_loads)),
                     "set_step_shape")
+
+    def get_step_shape(self, L, nvec, precision):
+        out = [c_int() for _ in range(5)]
+        self._check(LIB.polfed_get_step_shape(self.h, L, nvec, precision,
+                                              *[ctypes.byref(o) for o in out]), "get_step_shape")
+        return tuple(o.value for o in out)
 
     def set_block_size(self, L, precision, nev, block_size):
         self._check(LIB.polfed_set_block_size(self.h, L, precision, nev, block_size),

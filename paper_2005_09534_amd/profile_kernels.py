@@ -1,12 +1,15 @@
 """Profiling driver for the Chebyshev step kernel (run under rocprofv3).
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- \
-        python -m paper_2005_09534_amd.profile_kernels run --workload c2
+        python -m paper_2005_09534_amd.profile_kernels run --workload c2 --shape SHAPE
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT -o write -- \
-        python -m paper_2005_09534_amd.profile_kernels run --workload c2
-    python -m paper_2005_09534_amd.profile_kernels summarize --workload c2 \
+        python -m paper_2005_09534_amd.profile_kernels run --workload c2 --shape SHAPE
+    python -m paper_2005_09534_amd.profile_kernels summarize --workload c2 --shape SHAPE \
         --fetch OUT/.../fetch_counter_collection.csv --write OUT/.../write_counter_collection.csv \
         > profiles/k_step_c2_traffic.txt
+
+SHAPE is the step shape bench.py ran with (its config.step_shape, comma
+separated), so that the counters describe the launches the bench times.
 
 ``run`` applies the workload's filter (its chain, block width and precision)
 for a fixed number of steps, then copies a buffer of known size with a plain
@@ -55,6 +58,9 @@ def run(args):
     sigma = (2.0 * sigma_H - (E0w + E1w)) / (E1w - E0w)
     X = torch.randn((n, s), device="cuda", dtype=torch.float64).to(dt)
     Y = torch.empty_like(X)
+    if args.shape:
+        ctx.set_step_shape(c.L, s, 1 if wl.precision == "fp32" else 0,
+                           *[int(v) for v in args.shape.split(",")])
     ctx.set_graphs(False)  # one dispatch per step, each counted
     ctx.apply_filter(m, E0w, E1w, sigma, args.K, X, out=Y)
     torch.cuda.synchronize()
@@ -114,6 +120,7 @@ def summarize(args):
     print(f"hbm_fetch_bytes_per_launch = {fetch:.0f}")
     print(f"hbm_write_bytes_per_launch = {write:.0f}")
     print(f"hbm_bytes_per_launch = {fetch + write:.0f}")
+    print(f"step_shape = {args.shape}")
     print(f"kernel_source_sha256_16 = {kernel_source_hash()}")
 
 
@@ -123,10 +130,12 @@ def main():
     r = sub.add_parser("run")
     r.add_argument("--workload", default="c2")
     r.add_argument("--K", type=int, default=64)
+    r.add_argument("--shape", default="", help="threads,lpl,wg_per_cu,lds_tables,early_loads")
     s = sub.add_parser("summarize")
     s.add_argument("--workload", default="c2")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
+    s.add_argument("--shape", required=True, help="the shape given to run")
     a = ap.parse_args()
     sys.path.insert(0, ROOT)
     run(a) if a.cmd == "run" else summarize(a)

@@ -50,9 +50,12 @@ def test_tune_shape_and_block(ctx):
     from paper_2005_09534_amd import autotune, polfed as pf
     chains = [workloads.chain(10, 2.0, 50 + i) for i in range(3)]
     cache = {}
+    prior = ctx.get_step_shape(10, 4, 0)
     sh, gbs = autotune.tune_shape(ctx, chains[0], 4, 0, steps=8, shapes=autotune.SHAPES[:4],
                                   cache=cache)
-    assert sh in autotune.SHAPES[:4] and gbs > 0
+    # the shape in force is kept unless a candidate beats it by the margin
+    assert (sh == prior or sh in autotune.SHAPES[:4]) and gbs > 0
+    assert ctx.get_step_shape(10, 4, 0) == tuple(sh)
     best = autotune.tune_block(ctx, chains, 6, 0, widths=(2, 4), cache=cache)
     assert best is not None and best[0] in (2, 4)
     assert cache[autotune._key("block", 10, 0.0, 0, 6)][0] == best[0]
@@ -83,3 +86,12 @@ def test_early_loads_shape_in_a_solve(ctx, precision):
     assert np.abs(r["E"] - Ed).max() <= 1e-10 * normH
     res = np.linalg.norm(H @ r["V"] - r["V"] * r["E"], axis=0)
     assert res.max() <= 1e-8 * normH
+
+
+def test_get_step_shape_reports_what_is_in_force(ctx):
+    from paper_2005_09534_amd import autotune
+    sh = autotune.SHAPES[5]
+    ctx.set_step_shape(20, 8, 1, *sh)
+    assert ctx.get_step_shape(20, 8, 1) == tuple(sh)
+    d = ctx.get_step_shape(20, 8, 0)  # untouched entry: the built-in default
+    assert d[0] in (256, 1024) and d[1] in (1, 2, 4) and d[2] >= 1
