@@ -130,9 +130,11 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
       const uint32_t rot2 = ((s >> 2) | (s << (L - 2))) & fullmask;
       mm |= (unsigned long long)(s ^ rot2) << 32;
     }
-    while (mm) {
-      int32_t idx[kChunk];
-      bool two[kChunk];
+    // Neighbours go in chunks of kChunk: the rank-table lookups of chunk c+1
+    // are issued right after the gathers of chunk c, so each chunk costs one
+    // round of memory latency (lookups and gathers overlap) rather than two.
+    // Bits are taken in the same order either way, so the sum is unchanged.
+    auto fill = [&](int32_t(&idx)[kChunk], bool(&two)[kChunk]) {
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
         idx[u] = -1;
@@ -149,11 +151,20 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
           two[u] = (l == 2);
         }
       }
+    };
+    int32_t idx[kChunk];
+    bool two[kChunk];
+    fill(idx, two);
+    for (;;) {
       T nb[kChunk][VEC];
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
         if (idx[u] >= 0) load_row<T, VEC, LDV>(a.V + (size_t)idx[u] * a.ldv + col, nb[u]);
       }
+      const bool more = (mm != 0ull);
+      int32_t idx2[kChunk];
+      bool two2[kChunk];
+      fill(idx2, two2);  // no-op lookups when nothing is left
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
         if (idx[u] >= 0) {
@@ -161,6 +172,12 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
 #pragma unroll
           for (int e = 0; e < VEC; ++e) acc[e] += w * nb[u][e];
         }
+      }
+      if (!more) break;
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        idx[u] = idx2[u];
+        two[u] = two2[u];
       }
     }
   }

@@ -1197,32 +1197,25 @@ template void stage_apply_filter<double>(polfed_ctx *, const Chain &, double, do
 
 StepShape default_shape(int L, int S, bool fp32) {
   // From sweeps of (threads, loads per lane, groups per CU, LDS tables,
-  // early streamed loads) on gfx950 boxes: two 16-byte loads per lane are
-  // never worse than one by more than a few per cent and one load per lane
-  // was 2x slower on some boxes at L >= 18; chains up to L = 20 prefer
-  // sixteen 256-thread groups per CU with the rank tables read through the
-  // caches, and up to L = 18 (a step is about one round of memory latency)
-  // early streamed loads; L >= 22 prefers two 1024-thread groups per CU with
-  // the tables in LDS.  Short chains (L <= 16) sit at the launch floor.
+  // early streamed loads) on gfx950 boxes.  Short chains (L <= 16) sit at
+  // the launch floor (~6 us a step); one 16-byte load per lane and early
+  // streamed loads shave most off it.  From L = 18 on, eight 256-thread
+  // groups per CU with two loads per lane and the rank tables in LDS lead,
+  // except FP32 at L >= 22, where two 1024-thread groups per CU do.
   StepShape sh;
   sh.lds_tables = 1;
   sh.lpl = 2;
+  sh.threads = 256;
+  sh.wg_per_cu = 8;
   if (L <= 16) {
-    sh.threads = 256;
-    sh.wg_per_cu = 8;
     sh.lpl = 1;
     sh.lds_tables = 0;
-  } else if (L <= 20) {
-    sh.threads = 256;
-    sh.wg_per_cu = 16;
-    sh.lds_tables = 0;
-    sh.early_loads = (L <= 18) ? 1 : 0;
-  } else {
+    sh.early_loads = 1;
+  } else if (L >= 22 && fp32) {
     sh.threads = 1024;
     sh.wg_per_cu = 2;
   }
   (void)S;
-  (void)fp32;
   return sh;
 }
 
