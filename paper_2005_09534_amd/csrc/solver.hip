@@ -642,8 +642,16 @@ void Realization<T>::lanczos_step() {
     for (int i = 0; i < ms; ++i) above += theta[i] >= o.p;
     if (above < nev) thr = theta[std::max(0, ms - nev)];  // ascending order
     nconv = 0;
-    for (int i = 0; i < ms; ++i)
+    int nconv_loose = 0;
+    for (int i = 0; i < ms; ++i) {
       if (theta[i] >= thr && tres[i] <= tau) ++nconv;
+      if (theta[i] >= thr && tres[i] <= 30.0 * tau) ++nconv_loose;
+    }
+    // FP32 filter at the column cap: a Ritz pair whose estimate stalls above
+    // eps32 sqrt(K) (its rounding floor) still counts if it is within 30x of
+    // it; the FP64 refinement and the residual bar decide the result's
+    // accuracy (and an FP64 re-solve follows if it misses the bar)
+    if (fp32 && m_done >= m_max && nconv < nev && nconv_loose >= nev) nconv = nconv_loose;
     t_eig += now_s() - t2;
   }
   if (nconv >= nev || m_done >= m_max) done = true;
@@ -1197,20 +1205,18 @@ template void stage_apply_filter<double>(polfed_ctx *, const Chain &, double, do
 
 StepShape default_shape(int L, int S, bool fp32) {
   // From sweeps of (threads, loads per lane, groups per CU, LDS tables,
-  // early streamed loads) on gfx950 boxes.  Short chains (L <= 16) sit at
-  // the launch floor (~6 us a step); one 16-byte load per lane and early
-  // streamed loads shave most off it.  From L = 18 on, eight 256-thread
-  // groups per CU with two loads per lane and the rank tables in LDS lead,
-  // except FP32 at L >= 22, where two 1024-thread groups per CU do.
+  // early streamed loads) on gfx950 boxes: eight 256-thread groups per CU
+  // with the rank tables in LDS lead throughout; short rows (L <= 16, and
+  // FP32 at L = 18) want one 16-byte load per lane, the rest two; FP32 at
+  // L >= 22 prefers two 1024-thread groups per CU.  Short chains (L <= 16)
+  // sit near the launch floor (~5-6 us a step).
   StepShape sh;
   sh.lds_tables = 1;
   sh.lpl = 2;
   sh.threads = 256;
   sh.wg_per_cu = 8;
-  if (L <= 16) {
+  if (L <= 16 || (L == 18 && fp32)) {
     sh.lpl = 1;
-    sh.lds_tables = 0;
-    sh.early_loads = 1;
   } else if (L >= 22 && fp32) {
     sh.threads = 1024;
     sh.wg_per_cu = 2;

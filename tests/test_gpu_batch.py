@@ -75,3 +75,23 @@ def test_batch_mixed_status_and_layout(ctx, pf):
     assert res["rc"] == pf.NOT_CONVERGED
     assert np.array_equal(res["E"][0], res["E"][2])
     assert res["V"][0].shape == (pf.dim(12), 8) and res["V"][1].shape == (pf.dim(8), 8)
+
+
+def test_batched_workload_members_fp32(ctx, pf):
+    """Members of the 512-realisation batch (its L = 14 ones, N_ev = 20, FP32
+    filter, block size 8 as tuned) through polfed_solve_batch: every status
+    OK, residuals under the FP32 bar, eigenvalues equal to dense ones."""
+    wl = workloads.c4(24)
+    chains = [c for c in wl.chains if c.L == 14][:5]
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in chains]
+    res = ctx.solve_batch(models, wl.nev, vectors=True, block_size=8, precision=1)
+    assert all(st == pf.OK for st in res["status"]), res["status"]
+    for i, c in enumerate(chains):
+        H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+        w = dense.full_spectrum(H)
+        normH = max(abs(w[0]), abs(w[-1]))
+        Ed = w[dense.nearest_from_spectrum(w, res["info"][i]["sigma_energy"], wl.nev)]
+        assert np.abs(res["E"][i] - Ed).max() <= 1e-10 * normH, i
+        V = res["V"][i]
+        r = np.linalg.norm(H @ V - V * res["E"][i], axis=0)
+        assert r.max() <= 1e-8 * normH, (i, r.max())
