@@ -288,10 +288,17 @@ def main():
         torch.cuda.synchronize()
         t32 = time.perf_counter() - t0
         i32 = r32["info"]
+        import numpy as np
+        # eigenvector error against the FP64 solve: sine of the angle between
+        # corresponding vectors (the eigenvalues are simple here)
+        ov = np.abs(np.sum(r32["V"] * r["V"], axis=0))
+        sines = np.sqrt(np.clip(1.0 - ov * ov, 0.0, None))
         line["fp32_filter"] = {
             "time_to_nev_s": t32, "hv_apps_per_s": i32["hv_apps"] / t32,
             "max_resid_rel": i32["max_resid"] / i32["normH"], "refine_passes": i32["refine_passes"],
             "max_abs_eval_diff_vs_fp64": float(abs(r32["E"] - r["E"]).max()),
+            "max_evec_sin_angle_vs_fp64": float(sines.max()),
+            "speedup_vs_fp64": (wall / args.steps) / t32,
             "status": r32["status"]}
     line["gram"] = _gram_roofline(ctx, pf, pf.dim(c.L), int(last["m"]) * int(last["block_size"]),
                                   int(last["block_size"]))
