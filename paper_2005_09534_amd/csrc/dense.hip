@@ -469,7 +469,23 @@ __global__ void k_eig_sort(int n, const double *A, const double *Vin, double *w,
   for (int i = 0; i < n; ++i) Vout[(size_t)i * n + rk] = Vin[(size_t)i * n + t];
 }
 
-void sym_eig(hipStream_t st, int n, double *A, double *w, double *V, DevBuf &work) {
+// W = blockdiag(V0, I): V0 is n0 x n0 (ld n0), W is n x n.
+__global__ void k_embed_block(int n, int n0, const double *V0, double *W) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  W[e] = (i < n0 && j < n0) ? V0[(size_t)i * n0 + j] : (i == j ? 1.0 : 0.0);
+}
+
+void launch_embed_block(hipStream_t st, int n, int n0, const double *V0, double *W) {
+  const long long nn = (long long)n * n;
+  if (nn <= 0) return;
+  k_embed_block<<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(n, n0, V0, W);
+  check_launch("k_embed_block");
+}
+
+void sym_eig(hipStream_t st, int n, double *A, double *w, double *V, DevBuf &work,
+             const double *V0) {
   if (n <= 0) return;
   if (n > 4096) throw Error(POLFED_EINVAL, "sym_eig: n must be <= 4096");
   const size_t nn = (size_t)n * n;
@@ -478,8 +494,13 @@ void sym_eig(hipStream_t st, int n, double *A, double *w, double *V, DevBuf &wor
   double *A2 = base + nn;
   double *off = base + 2 * nn;
   double *buf[2] = {A, A2};
-  k_eye<<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(n, Vw);
-  check_launch("k_eye");
+  if (V0) {
+    // warm start: A is already V0^T A_orig V0, rotations accumulate onto V0
+    PF_HIP(hipMemcpyAsync(Vw, V0, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+  } else {
+    k_eye<<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(n, Vw);
+    check_launch("k_eye");
+  }
   const int m = n + (n & 1);
   const int npair = m / 2;
   const int tp = (npair + kJT - 1) / kJT;

@@ -162,7 +162,12 @@ void launch_update(hipStream_t st, long long n, int p, int q, double alpha, cons
                    long long ldx, const double *C, long long ldc, double beta, double *Y,
                    long long ldy);
 // Jacobi eigensolver; A (n x n) overwritten; w ascending, V columns.
-void sym_eig(hipStream_t st, int n, double *A, double *w, double *V, DevBuf &work);
+// V0 (nullable, n x n): warm start -- A holds V0^T A_orig V0 and the
+// returned V are eigenvectors of A_orig (rotations accumulate onto V0).
+void sym_eig(hipStream_t st, int n, double *A, double *w, double *V, DevBuf &work,
+             const double *V0 = nullptr);
+// W = blockdiag(V0 (n0 x n0), identity) as an n x n row-major matrix.
+void launch_embed_block(hipStream_t st, int n, int n0, const double *V0, double *W);
 // Cholesky of the s x s Gram matrix G (device, row-major, ld s):
 // writes Rinv = L^{-T} (upper) and B = L^T (upper), and flag[0] = index+1
 // of the first non-positive pivot (0 if fine).

@@ -392,6 +392,10 @@ struct Realization {
   std::vector<double> coef;
   double D = 1.0;
   DevBuf Qb, Tmb, dtb, Xb, Yb, Bb, coefb, chebb;
+  // eigenvectors of the T_m of the last convergence check (ms_prev x ms_prev),
+  // the warm start of the next check's eigensolve
+  DevBuf Vprevb, Wb;
+  int ms_prev = 0;
   int m_done = 0, nconv = 0, refills = 0;
   bool done = false;
   double t_start = 0, t_bounds = 0, t_filter = 0, t_orth = 0, t_eig = 0, bytes = 0;
@@ -627,7 +631,25 @@ void Realization<T>::lanczos_step() {
     double *Rres = static_cast<double *>(ctx->buf("Rres").ensure(sizeof(double) * (size_t)64 * P));
     PF_HIP(hipMemcpy2DAsync(Tw, sizeof(double) * ms, Tm(), sizeof(double) * P, sizeof(double) * ms,
                             ms, hipMemcpyDeviceToDevice, st));
-    sym_eig(st, ms, Tw, th, Vt, ctx->buf("eigwork"));
+    if (ms_prev > 0 && ms_prev == ms - s) {
+      // warm start: T_m = [[T_{m-1}, C], [C^T, A_m]] and T_{m-1} = V D V^T
+      // from the last check, so W^T T_m W with W = blockdiag(V, I) is
+      // diagonal but for its last s rows and columns; Jacobi on it needs
+      // far fewer sweeps.
+      double *W = static_cast<double *>(Wb.ensure(sizeof(double) * (size_t)P * P * 2));
+      double *tmp = W + (size_t)P * P;
+      launch_embed_block(st, ms, ms_prev, Vprevb.as<double>(), W);
+      launch_small_gemm(st, ms, ms, ms, Tw, ms, W, ms, tmp, ms, 0);
+      launch_small_gemm(st, ms, ms, ms, W, ms, tmp, ms, Tw, ms, 1);
+      launch_symmetrize(st, ms, Tw, ms);
+      sym_eig(st, ms, Tw, th, Vt, ctx->buf("eigwork"), W);
+    } else {
+      sym_eig(st, ms, Tw, th, Vt, ctx->buf("eigwork"));
+    }
+    Vprevb.ensure(sizeof(double) * (size_t)P * P);
+    PF_HIP(hipMemcpyAsync(Vprevb.p, Vt, sizeof(double) * (size_t)ms * ms, hipMemcpyDeviceToDevice,
+                          st));
+    ms_prev = ms;
     launch_small_gemm(st, s, s, ms, Bcur(), s, Vt + (size_t)(ms - s) * ms, ms, Rres, ms, 0);
     launch_colnorms(st, s, ms, Rres, ms, th + ms, partials, ctx->num_cu);
     std::vector<double> theta(ms), tres(ms);
