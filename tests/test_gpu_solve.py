@@ -205,3 +205,26 @@ def test_solve_deterministic(ctx, pf):
     a = ctx.solve(m, 10, block_size=4)
     b = ctx.solve(m, 10, block_size=4)
     assert (a["E"] == b["E"]).all() and (a["V"] == b["V"]).all()
+
+
+def test_solve_runs_at_the_largest_chain(ctx, pf):
+    """Every stage of the solve at L = 26 (10,400,600 rows; the FP32 path of
+    the L = 26 workload) with a forced short filter and two Lanczos blocks:
+    the run must come back (NOT_CONVERGED is expected at this size), and the
+    returned residuals must be those of the returned vectors, recomputed here
+    with the parity-tested H.V kernel."""
+    c = workloads.c5().chains[0]
+    m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
+    nev = 4
+    res = ctx.solve(m, nev, vectors=True, block_size=64, precision=1, K=32, max_cols=128)
+    assert res["status"] in (pf.OK, pf.NOT_CONVERGED)
+    info = res["info"]
+    assert info["K"] == 32 and info["m"] == 2
+    E, V, r = res["E"], res["V"], res["resid"]
+    assert np.all(np.isfinite(E)) and np.all(np.isfinite(r))
+    assert np.all((E >= info["E0w"]) & (E <= info["E1w"]))
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    HV = ctx.apply_h(m, Vd).cpu().numpy()
+    rr = np.linalg.norm(HV - V * E, axis=0)
+    np.testing.assert_allclose(rr, r, rtol=1e-6, atol=1e-12 * info["normH"])
+    np.testing.assert_allclose(np.linalg.norm(V, axis=0), 1.0, rtol=1e-12)
