@@ -247,7 +247,9 @@ int polfed_solve(polfed_ctx *ctx, const polfed_model *model,
  * many independent runs) solved together: models[R] may mix L.  evals and
  * resid are [R x nev] (realisation-major); evecs NULL or the concatenation
  * of the per-realisation [dim_r x nev] column-major blocks; infos (nullable)
- * [R]; status[R] per realisation.  Returns the worst status. */
+ * [R]; status[R] per realisation.  Returns the worst status.  R >= 1 and
+ * 1 <= nev <= dim_r for every model, checked before any work (else
+ * POLFED_EINVAL with the outputs untouched). */
 int polfed_solve_batch(polfed_ctx *ctx, int R, const polfed_model *models,
                        const polfed_opts *opts, int nev, double *evals,
                        double *evecs, double *resid, polfed_info *infos,

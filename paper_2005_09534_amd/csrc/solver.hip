@@ -1030,10 +1030,15 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
     PF_REQUIRE(d > 0, "invalid L in batch");
     voff[r + 1] = voff[r] + (size_t)d * nev;
   }
+  // every argument is checked before any work, so that an error leaves the
+  // outputs untouched
+  for (int r = 0; r < R; ++r) {
+    validate_model(&models[r]);
+    PF_REQUIRE(nev >= 1 && nev <= polfed_dim(models[r].L), "nev must be in [1, dim] for every model");
+  }
   // group by (L, block size)
   std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int r = 0; r < R; ++r) {
-    validate_model(&models[r]);
     const int s = o.block_size ? o.block_size : block_for(ctx, models[r].L, nev, o.precision);
     groups[{models[r].L, s}].push_back(r);
   }

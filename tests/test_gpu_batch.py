@@ -95,3 +95,15 @@ def test_batched_workload_members_fp32(ctx, pf):
         V = res["V"][i]
         r = np.linalg.norm(H @ V - V * res["E"][i], axis=0)
         assert r.max() <= 1e-8 * normH, (i, r.max())
+
+
+def test_batch_rejects_empty_and_oversized(ctx, pf):
+    """An empty batch and an N_ev above a member's dimension are argument
+    errors (nothing is computed)."""
+    with pytest.raises(pf.PolfedError):
+        ctx.solve_batch([], 4, block_size=4)
+    small = workloads.chain(6, 1.0, 3)  # dim 20
+    big = workloads.chain(10, 1.0, 4)
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in (big, small)]
+    with pytest.raises(pf.PolfedError):
+        ctx.solve_batch(models, 21, block_size=4)

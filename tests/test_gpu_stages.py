@@ -99,23 +99,25 @@ def test_apply_h_fp32(ctx, pf, L, nvec):
     assert np.abs(Y - ref).max() <= 2e-6 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("nvec,dtype", [(64, np.float32), (16, np.float64)])
-def test_apply_h_L26_sampled_rows(ctx, pf, nvec, dtype):
-    """Full-size chain (L=26, 10,400,600 rows, the launch shape of the
-    L=26 workload): 300 sampled rows against the oracle's per-row form."""
-    wl = workloads.c5()
+@pytest.mark.parametrize("L,nvec,dtype", [(26, 64, np.float32), (26, 16, np.float64),
+                                          (22, 32, np.float32), (22, 32, np.float64)])
+def test_apply_h_large_sampled_rows(ctx, pf, L, nvec, dtype):
+    """Full-size chains (L=22: 705,432 rows; L=26: 10,400,600 rows; the
+    widths of those workloads): 300 sampled rows against the oracle's
+    per-row form."""
+    wl = workloads.c5() if L == 26 else workloads.c3()
     c = wl.chains[0]
     m = _model(pf, c)
-    n = pf.dim(26)
+    n = pf.dim(L)
     g = torch.Generator(device="cuda").manual_seed(9)
     X = torch.randn((n, nvec), generator=g, device="cuda", dtype=torch.float64).to(
         torch.float32 if dtype == np.float32 else torch.float64)
     Y = ctx.apply_h(m, X)
-    b = chain.basis(26)
+    b = chain.basis(L)
     rows = np.unique(np.concatenate([[0, 1, n - 1], np.random.default_rng(1).integers(0, n, 297)]))
     Xs = X.to(torch.float64)
     for r in rows:
-        ent = chain.hamiltonian_row(26, c.J1, c.J2, c.Delta, c.h, b[r])
+        ent = chain.hamiltonian_row(L, c.J1, c.J2, c.Delta, c.h, b[r])
         cols = chain.rank(np.array(list(ent.keys()), dtype=np.uint32), b)
         vals = torch.tensor(list(ent.values()), dtype=torch.float64, device="cuda")
         ref = (vals[:, None] * Xs[torch.from_numpy(cols).cuda()]).sum(0)
@@ -300,3 +302,32 @@ def test_bounds(ctx, pf, L, J2):
     assert E0x - 1e-9 <= E0 <= E0x + r0 + 1e-9
     assert E1x - r1 - 1e-9 <= E1 <= E1x + 1e-9
     assert abs(E0 - E0x) < 1e-6 * abs(E0x) and abs(E1 - E1x) < 1e-6 * abs(E1x)
+
+
+def test_filter_fp32_vs_fp64_at_the_l22_order(ctx, pf):
+    """The L=22 workload's own filter (its chain, widened Lanczos bounds, the
+    target at the middle of the spectrum, the order K the solve picks for
+    N_win = 150, block width 32): the FP32 filter matches the FP64 one to
+    1e-4 relative per column, and the FP64 filter is symmetric (X^T P X)."""
+    wl = workloads.c3("fp32")
+    c = wl.chains[0]
+    m = _model(pf, c)
+    n = pf.dim(c.L)
+    E0, E1, r0, r1 = ctx.bounds(m, 200)
+    w = E1 - E0
+    E0w, E1w = E0 - r0 - 1e-3 * w, E1 + r1 + 1e-3 * w
+    sig = (2.0 * (E0 + 0.5 * w) - (E0w + E1w)) / (E1w - E0w)
+    K, _ = pf.filter_order(m, E0w, E1w, sig, 150)
+    assert 20000 < K < 80000
+    g = torch.Generator(device="cuda").manual_seed(3)
+    X = torch.randn((n, 32), generator=g, device="cuda", dtype=torch.float64)
+    X /= X.norm(dim=0)
+    Y64 = ctx.apply_filter(m, E0w, E1w, sig, K, X)
+    Y32 = ctx.apply_filter(m, E0w, E1w, sig, K, X.to(torch.float32)).to(torch.float64)
+    rel = ((Y32 - Y64).norm(dim=0) / Y64.norm(dim=0)).max().item()
+    print(f"L=22 K={K}: FP32 vs FP64 filter, max column relative difference {rel:.2e}")
+    assert rel <= 1e-4
+    G = (X.T @ Y64).cpu().numpy()
+    assert np.abs(G - G.T).max() <= 1e-10 * np.abs(G).max()
+    del X, Y64, Y32
+    torch.cuda.empty_cache()
