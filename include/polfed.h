@@ -74,7 +74,7 @@ typedef struct {
                              Rayleigh-Ritz and residuals + FP64 refinement  */
   double window_factor;   /* filter window sized for ceil(f N_ev)
                              eigenvalues; 0 -> 1.5                          */
-  int max_cols;           /* Lanczos columns; 0 -> 6 N_win + 6 s           */
+  int max_cols;           /* Lanczos columns; 0 -> 8 N_win + 8 s           */
   double tol;             /* residual target relative to ||H||; 0 -> 1e-10 */
   double eta;             /* bounds margin, fraction of E1-E0; 0 -> 1e-3   */
   int bounds_steps;       /* bounds Lanczos steps; 0 -> 200                 */

@@ -174,14 +174,15 @@ def window_count(nev, factor=1.5):
 
 
 def column_cap(nwin, s):
-    """Lanczos columns allocated: 6 N_win + 6s, in whole blocks.  The paper
+    """Lanczos columns allocated: 8 N_win + 8s, in whole blocks.  The paper
     allocates 2.8 N_ev columns, a bound it states for s <= 24 and
     N_ev >= 1000; at the N_ev = 8..100 of the workloads here convergence
     was observed to need up to ~5 N_ev columns with s = 4, ~12 blocks when s
     is as large as N_ev, and more when the window holds fewer than N_ev
     eigenvalues above p (Gaussian DOS overestimated) and the N_ev-th must
-    converge from below p."""
-    cols = 6 * nwin + 6 * s
+    converge from below p: one L = 18, N_ev = 20, s = 8 realisation of 170
+    needed 248 columns (8.3 N_win)."""
+    cols = 8 * nwin + 8 * s
     return -(-cols // s) * s
 
 

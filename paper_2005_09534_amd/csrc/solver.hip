@@ -460,8 +460,8 @@ void Realization<T>::setup(polfed_ctx *ctx_, const polfed_model *model, const po
     K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, &rho);
   }
   cheb_coeffs(sigma, K, coef, D);
-  // column cap: 6 N_win + 6 s in whole blocks, at most n
-  long long cols = (o.max_cols > 0) ? o.max_cols : 6LL * nwin + 6LL * s;
+  // column cap: 8 N_win + 8 s in whole blocks, at most n
+  long long cols = (o.max_cols > 0) ? o.max_cols : 8LL * nwin + 8LL * s;
   cols = std::min<long long>(cols, (n / s) * s);
   m_max = (int)std::max<long long>(1, cols / s);
   P = m_max * s;
