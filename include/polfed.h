@@ -47,7 +47,8 @@ enum polfed_status {
   POLFED_EINVAL = -1,       /* invalid argument (message says which)     */
   POLFED_ENOMEM = -2,       /* device allocation failed                  */
   POLFED_EDEVICE = -3,      /* HIP runtime error                         */
-  POLFED_EBOUNDS = -4,      /* spectral bounds too tight: filter blew up */
+  POLFED_EBOUNDS = -4,      /* spectral bounds too tight: filter blew up
+                               (checked on every Lanczos block)           */
   POLFED_EBREAKDOWN = -5    /* Lanczos block could not be refilled       */
 };
 

@@ -595,6 +595,20 @@ void Realization<T>::lanczos_step() {
   if (j > 0) launch_update(st, n, s, s, -1.0, Q() + (size_t)(j - 1) * s, P, BT(), s, 1.0, U, s);
   launch_gram(st, n, s, s, Qj, P, U, s, Ablk, s, partials, ctx->num_cu);
   launch_symmetrize(st, s, Ablk, s);
+  {
+    // bounds guard: A_j = Q_j^T P(H~) Q_j has entries of size <= max|P| on
+    // the spectrum, about 1 when [E0w, E1w] encloses it; outside [-1, 1] the
+    // Chebyshev terms grow like cosh(K acosh|x|), so an eigenvalue beyond the
+    // widened bounds shows up here as huge or non-finite entries
+    std::vector<double> ha((size_t)s * s);
+    PF_HIP(hipMemcpyAsync(ha.data(), Ablk, sizeof(double) * s * s, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipStreamSynchronize(st));
+    for (double v : ha)
+      if (!(std::fabs(v) <= 4.0))
+        throw Error(POLFED_EBOUNDS,
+                    "filter left [-1, 1]: the spectrum extends beyond the widened Lanczos "
+                    "bounds (raise bounds_steps or eta)");
+  }
   launch_update(st, n, s, s, -1.0, Qj, P, Ablk, s, 1.0, U, s);
   PF_HIP(hipMemcpy2DAsync(Tm() + (size_t)j * s * P + j * s, sizeof(double) * P, Ablk,
                           sizeof(double) * s, sizeof(double) * s, s, hipMemcpyDeviceToDevice, st));
@@ -772,7 +786,6 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
     std::vector<int> cand;
     for (int i = 0; i < ms; ++i)
       if (theta[i] >= o.p) cand.push_back(i);
-    const int above = (int)cand.size();
     // at least nev candidates (the nev largest theta when fewer pass p)
     const int want = nev;
     if ((int)cand.size() < want) {
@@ -846,7 +859,6 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
     const double target = std::max(o.tol, 5e-9) * normH;
     const long long K_ref = K;
     long long K_r = std::max<long long>(16, K_ref / 4);
-    (void)above;
     std::vector<double> coef_r;
     double D_r = 1.0;
     double *Vn = static_cast<double *>(ctx->buf("Vn").ensure(sizeof(double) * (size_t)n * ldr));
@@ -1046,7 +1058,6 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
   for (auto &g : groups) {
     const std::vector<int> &mem = g.second;
     const int B = (int)mem.size();
-    const double tg0 = now_s();
     std::vector<std::unique_ptr<Realization<T>>> rs(B);
     polfed_opts og = o;
     og.block_size = g.first.second;
@@ -1091,7 +1102,7 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
     hipEvent_t e0, e1;
     PF_HIP(hipEventCreate(&e0));
     PF_HIP(hipEventCreate(&e1));
-    double gfilter = 0.0, gbytes = 0.0, glaunch = 0.0;
+    double gfilter = 0.0, glaunch = 0.0;
     try {
       for (;;) {
         int nact = 0;
@@ -1149,7 +1160,6 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
           }
           mv += (double)n * (S * (double)sizeof(T) * (2 + (K >= 1) + (K >= 2)) +
                              (K >= 1 ? 4.0 + sizeof(T) : 0.0));
-          gbytes += mv;
           rs[i]->bytes += mv;
         }
         const double tf = now_s() - tf0;
@@ -1181,8 +1191,6 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
       status[r] = rc;
       if (rc > 0 && worst == POLFED_OK) worst = rc;
     }
-    (void)tg0;
-    (void)gbytes;
   }
   return worst;
 }

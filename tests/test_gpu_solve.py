@@ -228,3 +228,26 @@ def test_solve_runs_at_the_largest_chain(ctx, pf):
     rr = np.linalg.norm(HV - V * E, axis=0)
     np.testing.assert_allclose(rr, r, rtol=1e-6, atol=1e-12 * info["normH"])
     np.testing.assert_allclose(np.linalg.norm(V, axis=0), 1.0, rtol=1e-12)
+
+
+@pytest.mark.parametrize("steps", [2, 3, 5])
+def test_poor_bounds_never_return_garbage(ctx, pf, steps):
+    """With very few bounds-Lanczos steps the widened bounds may miss part of
+    the spectrum; the solve must then fail with POLFED_EBOUNDS (the filter
+    left [-1, 1]) or still return the dense answer -- never wrong pairs."""
+    c = workloads.chain(10, 2.0, 21)
+    H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+    w = dense.full_spectrum(H)
+    normH = max(abs(w[0]), abs(w[-1]))
+    m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
+    try:
+        r = ctx.solve(m, 6, block_size=2, bounds_steps=steps, vectors=True)
+    except pf.PolfedError as e:
+        assert e.code == pf.EBOUNDS, e
+        return
+    info = r["info"]
+    if r["status"] == pf.OK:
+        Ed = w[dense.nearest_from_spectrum(w, info["sigma_energy"], 6)]
+        assert np.abs(r["E"] - Ed).max() <= 1e-10 * normH
+    res = np.linalg.norm(H @ r["V"] - r["V"] * r["E"], axis=0)
+    np.testing.assert_allclose(res, r["resid"], rtol=1e-6, atol=1e-12 * normH)
