@@ -363,6 +363,8 @@ __device__ __forceinline__ void jacobi_rotation(const double *A, int n, int m, i
 // thread, 16 x 16 pair-blocks per workgroup) and V <- V J in place (16 rows
 // x 16 pairs per workgroup).  Workgroups [0, nta) do A tiles, the rest V.
 constexpr int kJT = 16;
+// Largest matrix the batched LDS Jacobi takes (n^2 doubles + 16 KB of LDS).
+constexpr int kLdsEigMax = 128;
 
 __global__ __launch_bounds__(256) void k_jacobi_round(int n, int r, const double *Ain,
                                                       double *Aout, double *V, int tiles_a) {
@@ -421,6 +423,128 @@ __global__ __launch_bounds__(256) void k_jacobi_round(int n, int r, const double
     V[(size_t)i * n + p] = c * vp - s * vq;
     V[(size_t)i * n + q] = s * vp + c * vq;
   }
+}
+
+// Batched cyclic Jacobi for many small symmetric matrices of one size: one
+// workgroup per matrix with the matrix in LDS, the eigenvectors accumulated
+// in global memory.  The rotations (round-robin pairs, same formula as
+// jacobi_rotation), the in-place 2 x 2 block updates and the stopping rule
+// are those of sym_eig, applied to each matrix on its own, so that many
+// Lanczos convergence checks of one batch run in a single launch.
+__global__ __launch_bounds__(1024) void k_jacobi_lds(int n, double *A, double *V, double *w,
+                                                     double *Vout, int max_sweeps) {
+  extern __shared__ double sA[];  // n * n, then 2 * 1024 for reductions
+  __shared__ int sp[kLdsEigMax / 2], sq[kLdsEigMax / 2];
+  __shared__ double sc[kLdsEigMax / 2], ss[kLdsEigMax / 2];
+  __shared__ int s_stop;
+  double *red = sA + (size_t)n * n;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const size_t nn = (size_t)n * n;
+  double *Ab = A + (size_t)blockIdx.x * nn;
+  double *Vb = V + (size_t)blockIdx.x * nn;
+  for (size_t e = t; e < nn; e += nt) sA[e] = Ab[e];
+  __syncthreads();
+  const int m = n + (n & 1);
+  const int npair = m / 2;
+  double prev = -1.0;
+  for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+    for (int r = 0; r < m - 1; ++r) {
+      if (t < npair) {
+        int p, q;
+        double c, sn;
+        jacobi_rotation(sA, n, m, r, t, p, q, c, sn);
+        sp[t] = p;
+        sq[t] = q;
+        sc[t] = c;
+        ss[t] = sn;
+      }
+      __syncthreads();
+      // A <- J^T A J: the 2 x 2 blocks (pair k1 rows, pair k2 columns) are
+      // disjoint, each read and written by one thread
+      for (int idx = t; idx < npair * npair; idx += nt) {
+        const int k1 = idx / npair, k2 = idx % npair;
+        const int p1 = sp[k1], q1 = sq[k1], p2 = sp[k2], q2 = sq[k2];
+        const double c1 = sc[k1], s1 = ss[k1], c2 = sc[k2], s2 = ss[k2];
+        const bool q1ok = q1 < n, q2ok = q2 < n;
+        const double a00 = sA[(size_t)p1 * n + p2];
+        const double a01 = q2ok ? sA[(size_t)p1 * n + q2] : 0.0;
+        const double a10 = q1ok ? sA[(size_t)q1 * n + p2] : 0.0;
+        const double a11 = (q1ok && q2ok) ? sA[(size_t)q1 * n + q2] : 0.0;
+        const double b00 = c1 * a00 - s1 * a10, b01 = c1 * a01 - s1 * a11;
+        const double b10 = s1 * a00 + c1 * a10, b11 = s1 * a01 + c1 * a11;
+        sA[(size_t)p1 * n + p2] = b00 * c2 - b01 * s2;
+        if (q2ok) sA[(size_t)p1 * n + q2] = b00 * s2 + b01 * c2;
+        if (q1ok) sA[(size_t)q1 * n + p2] = b10 * c2 - b11 * s2;
+        if (q1ok && q2ok) sA[(size_t)q1 * n + q2] = b10 * s2 + b11 * c2;
+      }
+      // V <- V J (columns p, q of every row)
+      for (int idx = t; idx < n * npair; idx += nt) {
+        const int i = idx / npair, k = idx % npair;
+        const int p = sp[k], q = sq[k];
+        if (q >= n) continue;
+        const double c = sc[k], sn = ss[k];
+        const double vp = Vb[(size_t)i * n + p], vq = Vb[(size_t)i * n + q];
+        Vb[(size_t)i * n + p] = c * vp - sn * vq;
+        Vb[(size_t)i * n + q] = sn * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    // off-diagonal and diagonal sums of squares
+    double off = 0.0, dg = 0.0;
+    for (size_t e = t; e < nn; e += nt) {
+      const double v = sA[e];
+      if (e / n == e % n) dg += v * v; else off += v * v;
+    }
+    red[t] = off;
+    red[1024 + t] = dg;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+      if (t < h && t + h < nt) {
+        red[t] += red[t + h];
+        red[1024 + t] += red[1024 + t + h];
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      const double o = red[0], d = red[1024];
+      int stop = (!(o > 1e-28 * d) || o == 0.0) ? 1 : 0;
+      if (prev >= 0.0 && sweep >= 3 && o > 0.5 * prev) stop = 1;
+      s_stop = stop;
+      red[0] = o;  // kept for prev
+    }
+    __syncthreads();
+    prev = red[0];
+    const int stop = s_stop;
+    __syncthreads();
+    if (stop) break;
+  }
+  // eigenvalues ascending (ties by index) and the matching columns of V
+  double *wb = w + (size_t)blockIdx.x * n;
+  double *Vo = Vout + (size_t)blockIdx.x * nn;
+  for (int i = t; i < n; i += nt) {
+    const double di = sA[(size_t)i * n + i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double dj = sA[(size_t)j * n + j];
+      rank += (dj < di || (dj == di && j < i)) ? 1 : 0;
+    }
+    wb[rank] = di;
+    for (int row = 0; row < n; ++row) Vo[(size_t)row * n + rank] = Vb[(size_t)row * n + i];
+  }
+}
+
+bool sym_eig_batched(hipStream_t st, int n, int B, double *A, double *V, double *w,
+                     double *Vout) {
+  if (n < 1 || n > kLdsEigMax || B < 1) return false;
+  const size_t shm = sizeof(double) * ((size_t)n * n + 2 * 1024);
+  if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_jacobi_lds),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  k_jacobi_lds<<<B, 1024, shm, st>>>(n, A, V, w, Vout, 40);
+  check_launch("k_jacobi_lds");
+  return true;
 }
 
 // off-diagonal and diagonal sums of squares -> out[0], out[1] (one block)

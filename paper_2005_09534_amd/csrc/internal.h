@@ -166,6 +166,13 @@ void launch_update(hipStream_t st, long long n, int p, int q, double alpha, cons
 // returned V are eigenvectors of A_orig (rotations accumulate onto V0).
 void sym_eig(hipStream_t st, int n, double *A, double *w, double *V, DevBuf &work,
              const double *V0 = nullptr);
+// B symmetric n x n matrices at once (n <= 128, one workgroup each, matrix
+// in LDS): A (B x n x n, destroyed), V (B x n x n) the starting vectors
+// (identity, or a warm start with A already rotated), outputs w (B x n,
+// ascending) and Vout (B x n x n, columns = eigenvectors).  Returns false
+// (nothing launched) when n is too large or the LDS cannot be granted.
+bool sym_eig_batched(hipStream_t st, int n, int B, double *A, double *V, double *w,
+                     double *Vout);
 // W = blockdiag(V0 (n0 x n0), identity) as an n x n row-major matrix.
 void launch_embed_block(hipStream_t st, int n, int n0, const double *V0, double *W);
 // Cholesky of the s x s Gram matrix G (device, row-major, ld s):

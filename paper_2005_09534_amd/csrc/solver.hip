@@ -396,7 +396,7 @@ struct Realization {
   DevBuf Qb, Tmb, dtb, Xb, Yb, Bb, coefb, chebb;
   // eigenvectors of the T_m of the last convergence check (ms_prev x ms_prev),
   // the warm start of the next check's eigensolve
-  DevBuf Vprevb, Wb;
+  DevBuf Vprevb, thprevb, Wb;
   int ms_prev = 0;
   int m_done = 0, nconv = 0, refills = 0;
   bool done = false;
@@ -414,6 +414,16 @@ struct Realization {
   void setup(polfed_ctx *ctx_, const polfed_model *model, const polfed_opts &o_, int nev_);
   const T *filter_X();
   void lanczos_step();
+  // lanczos_step in parts, for the batch driver: the block (Lan1,
+  // reorthogonalisation, QR, T_m), returning whether a convergence check is
+  // due; the check's eigenproblem (T_m, or W^T T_m W for a warm start, into
+  // A and its starting vectors into V0, both ms x ms); and the check itself
+  // from the eigenpairs (th ascending, Vt columns).
+  bool lanczos_block();
+  int check_size() const { return m_done * s; }
+  void check_prepare(double *A, double *V0);
+  void check_finish(const double *th, const double *Vt);
+  void check_single();  // prepare, sym_eig, finish
   int finalize(double *evals, double *evecs, double *resid, polfed_info *info);
 
  private:
@@ -582,7 +592,7 @@ const T *Realization<T>::filter_X() {
 // eqs. (Lan1)-(Lan2) with full reorthogonalisation, T_m, and the
 // convergence test on the eigenpairs of T_m.
 template <class T>
-void Realization<T>::lanczos_step() {
+bool Realization<T>::lanczos_block() {
   hipStream_t st = ctx->stream;
   DevBuf &partials = ctx->buf("partials");
   const int j = m_done;
@@ -638,64 +648,95 @@ void Realization<T>::lanczos_step() {
   m_done = j + 1;
   const int ms = m_done * s;
   const int check_from = std::max(s, std::min(nev, P));
-  if (ms >= check_from || m_done == m_max) {
-    // eigenpairs of T_m; residual_i = ||B_{j+1} t~_i||, t~_i the last s
-    // components of t_i
-    double *Tw = static_cast<double *>(ctx->buf("Tw").ensure(sizeof(double) * (size_t)P * P));
-    double *Vt = static_cast<double *>(ctx->buf("Vt").ensure(sizeof(double) * (size_t)P * P));
-    double *th = static_cast<double *>(ctx->buf("theta").ensure(sizeof(double) * (size_t)P * 2));
-    double *Rres = static_cast<double *>(ctx->buf("Rres").ensure(sizeof(double) * (size_t)64 * P));
-    PF_HIP(hipMemcpy2DAsync(Tw, sizeof(double) * ms, Tm(), sizeof(double) * P, sizeof(double) * ms,
-                            ms, hipMemcpyDeviceToDevice, st));
-    if (ms_prev > 0 && ms_prev == ms - s) {
-      // warm start: T_m = [[T_{m-1}, C], [C^T, A_m]] and T_{m-1} = V D V^T
-      // from the last check, so W^T T_m W with W = blockdiag(V, I) is
-      // diagonal but for its last s rows and columns; Jacobi on it needs
-      // far fewer sweeps.
-      double *W = static_cast<double *>(Wb.ensure(sizeof(double) * (size_t)P * P * 2));
-      double *tmp = W + (size_t)P * P;
-      launch_embed_block(st, ms, ms_prev, Vprevb.as<double>(), W);
-      launch_small_gemm(st, ms, ms, ms, Tw, ms, W, ms, tmp, ms, 0);
-      launch_small_gemm(st, ms, ms, ms, W, ms, tmp, ms, Tw, ms, 1);
-      launch_symmetrize(st, ms, Tw, ms);
-      sym_eig(st, ms, Tw, th, Vt, ctx->buf("eigwork"), W);
-    } else {
-      sym_eig(st, ms, Tw, th, Vt, ctx->buf("eigwork"));
-    }
-    Vprevb.ensure(sizeof(double) * (size_t)P * P);
-    PF_HIP(hipMemcpyAsync(Vprevb.p, Vt, sizeof(double) * (size_t)ms * ms, hipMemcpyDeviceToDevice,
-                          st));
-    ms_prev = ms;
-    launch_small_gemm(st, s, s, ms, Bcur(), s, Vt + (size_t)(ms - s) * ms, ms, Rres, ms, 0);
-    launch_colnorms(st, s, ms, Rres, ms, th + ms, partials, ctx->num_cu);
-    std::vector<double> theta(ms), tres(ms);
-    PF_HIP(hipMemcpyAsync(theta.data(), th, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
-    PF_HIP(hipMemcpyAsync(tres.data(), th + ms, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
-    PF_HIP(hipStreamSynchronize(st));
-    // converged: theta_i >= p and ||B t~_i|| <= tau; when fewer than nev
-    // Ritz values exceed p (the Gaussian DOS overestimated the window), the
-    // nev largest theta take their place
-    double thr = o.p;
-    int above = 0;
-    for (int i = 0; i < ms; ++i) above += theta[i] >= o.p;
-    if (above < nev) thr = theta[std::max(0, ms - nev)];  // ascending order
-    nconv = 0;
-    int nconv_loose = 0;
-    for (int i = 0; i < ms; ++i) {
-      if (theta[i] >= thr && tres[i] <= tau) ++nconv;
-      if (theta[i] >= thr && tres[i] <= 30.0 * tau) ++nconv_loose;
-    }
-    // FP32 filter at the column cap: a Ritz pair whose estimate stalls above
-    // eps32 sqrt(K) (its rounding floor) still counts if it is within 30x of
-    // it; the FP64 refinement and the residual bar decide the result's
-    // accuracy (and an FP64 re-solve follows if it misses the bar)
-    if (fp32 && m_done >= m_max && nconv < nev && nconv_loose >= nev) nconv = nconv_loose;
-    t_eig += now_s() - t2;
+  const bool due = (ms >= check_from || m_done == m_max);
+  if (!due && m_done >= m_max) done = true;
+  return due;
+}
+
+template <class T>
+void Realization<T>::check_prepare(double *A, double *V0) {
+  hipStream_t st = ctx->stream;
+  const int ms = m_done * s;
+  PF_HIP(hipMemcpy2DAsync(A, sizeof(double) * ms, Tm(), sizeof(double) * P, sizeof(double) * ms, ms,
+                          hipMemcpyDeviceToDevice, st));
+  if (ms_prev > 0 && ms_prev == ms - s) {
+    // warm start: T_m = [[T_{m-1}, C], [C^T, A_m]] and T_{m-1} = V D V^T
+    // from the last check, so W^T T_m W with W = blockdiag(V, I) is diagonal
+    // but for its last s rows and columns; Jacobi on it needs far fewer
+    // sweeps
+    double *tmp = static_cast<double *>(Wb.ensure(sizeof(double) * (size_t)P * P));
+    launch_embed_block(st, ms, ms_prev, Vprevb.as<double>(), V0);
+    launch_small_gemm(st, ms, ms, ms, A, ms, V0, ms, tmp, ms, 0);
+    launch_small_gemm(st, ms, ms, ms, V0, ms, tmp, ms, A, ms, 1);
+    launch_symmetrize(st, ms, A, ms);
+  } else {
+    launch_embed_block(st, ms, 0, nullptr, V0);  // identity
   }
+}
+
+template <class T>
+void Realization<T>::check_finish(const double *th, const double *Vt) {
+  hipStream_t st = ctx->stream;
+  DevBuf &partials = ctx->buf("partials");
+  const int ms = m_done * s;
+  const double t2 = now_s();
+  Vprevb.ensure(sizeof(double) * (size_t)P * P);
+  thprevb.ensure(sizeof(double) * (size_t)P);
+  PF_HIP(hipMemcpyAsync(thprevb.p, th, sizeof(double) * (size_t)ms, hipMemcpyDeviceToDevice, st));
+  PF_HIP(hipMemcpyAsync(Vprevb.p, Vt, sizeof(double) * (size_t)ms * ms, hipMemcpyDeviceToDevice, st));
+  ms_prev = ms;
+  // residual_i = ||B_{j+1} t~_i||, t~_i the last s components of t_i
+  double *Rres = static_cast<double *>(ctx->buf("Rres").ensure(sizeof(double) * (size_t)64 * P));
+  double *tr = static_cast<double *>(ctx->buf("tres").ensure(sizeof(double) * (size_t)P));
+  launch_small_gemm(st, s, s, ms, Bcur(), s, Vt + (size_t)(ms - s) * ms, ms, Rres, ms, 0);
+  launch_colnorms(st, s, ms, Rres, ms, tr, partials, ctx->num_cu);
+  std::vector<double> theta(ms), tres(ms);
+  PF_HIP(hipMemcpyAsync(theta.data(), th, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipMemcpyAsync(tres.data(), tr, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
+  // converged: theta_i >= p and ||B t~_i|| <= tau; when fewer than nev
+  // Ritz values exceed p (the Gaussian DOS overestimated the window), the
+  // nev largest theta take their place
+  double thr = o.p;
+  int above = 0;
+  for (int i = 0; i < ms; ++i) above += theta[i] >= o.p;
+  if (above < nev) thr = theta[std::max(0, ms - nev)];  // ascending order
+  nconv = 0;
+  int nconv_loose = 0;
+  for (int i = 0; i < ms; ++i) {
+    if (theta[i] >= thr && tres[i] <= tau) ++nconv;
+    if (theta[i] >= thr && tres[i] <= 30.0 * tau) ++nconv_loose;
+  }
+  // FP32 filter at the column cap: a Ritz pair whose estimate stalls above
+  // eps32 sqrt(K) (its rounding floor) still counts if it is within 30x of
+  // it; the FP64 refinement and the residual bar decide the result's
+  // accuracy (and an FP64 re-solve follows if it misses the bar)
+  if (fp32 && m_done >= m_max && nconv < nev && nconv_loose >= nev) nconv = nconv_loose;
+  t_eig += now_s() - t2;
   if (nconv >= nev || m_done >= m_max) done = true;
   if (std::getenv("POLFED_VERBOSE"))
     fprintf(stderr, "[polfed] L=%d block %d/%d: %d of %d converged (filter %.2f s so far)\n", c.L,
             m_done, m_max, nconv, nev, t_filter);
+}
+
+
+template <class T>
+void Realization<T>::lanczos_step() {
+  if (lanczos_block()) check_single();
+}
+
+template <class T>
+void Realization<T>::check_single() {
+  const double t2 = now_s();
+  const int ms = m_done * s;
+  double *Tw = static_cast<double *>(ctx->buf("Tw").ensure(sizeof(double) * (size_t)P * P));
+  double *Vt = static_cast<double *>(ctx->buf("Vt").ensure(sizeof(double) * (size_t)P * P));
+  double *V0 = static_cast<double *>(ctx->buf("V0").ensure(sizeof(double) * (size_t)P * P));
+  double *th = static_cast<double *>(ctx->buf("theta").ensure(sizeof(double) * (size_t)P));
+  check_prepare(Tw, V0);
+  sym_eig(ctx->stream, ms, Tw, th, Vt, ctx->buf("eigwork"), V0);
+  t_eig += now_s() - t2;
+  check_finish(th, Vt);
 }
 
 template <class T>
@@ -713,9 +754,16 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
   double *Tw = static_cast<double *>(ctx->buf("Tw").ensure(sizeof(double) * (size_t)P * P));
   double *Vt = static_cast<double *>(ctx->buf("Vt").ensure(sizeof(double) * (size_t)P * P));
   double *th = static_cast<double *>(ctx->buf("theta").ensure(sizeof(double) * (size_t)P * 2));
-  PF_HIP(hipMemcpy2DAsync(Tw, sizeof(double) * ms, Tm(), sizeof(double) * P, sizeof(double) * ms, ms,
-                          hipMemcpyDeviceToDevice, st));
-  sym_eig(st, ms, Tw, th, Vt, eigwork);
+  if (ms_prev == ms) {
+    // the last convergence check decomposed this very T_m
+    PF_HIP(hipMemcpyAsync(Vt, Vprevb.p, sizeof(double) * (size_t)ms * ms, hipMemcpyDeviceToDevice,
+                          st));
+    PF_HIP(hipMemcpyAsync(th, thprevb.p, sizeof(double) * (size_t)ms, hipMemcpyDeviceToDevice, st));
+  } else {
+    PF_HIP(hipMemcpy2DAsync(Tw, sizeof(double) * ms, Tm(), sizeof(double) * P, sizeof(double) * ms,
+                            ms, hipMemcpyDeviceToDevice, st));
+    sym_eig(st, ms, Tw, th, Vt, eigwork);
+  }
   std::vector<double> theta(ms);
   PF_HIP(hipMemcpyAsync(theta.data(), th, sizeof(double) * ms, hipMemcpyDeviceToHost, st));
   PF_HIP(hipStreamSynchronize(st));
@@ -1169,8 +1217,37 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
         const double tf = now_s() - tf0;
         for (int i = 0; i < B; ++i)
           if (items[i].active) rs[i]->t_filter += tf / nact;
+        // every active member's block, then their convergence checks: the
+        // members advance in lock step, so the checks share one size and
+        // their eigenproblems run in one batched launch when small enough
+        std::vector<int> due;
         for (int i = 0; i < B; ++i)
-          if (items[i].active) rs[i]->lanczos_step();
+          if (items[i].active && rs[i]->lanczos_block()) due.push_back(i);
+        if (!due.empty()) {
+          const int msz = rs[due[0]]->check_size();
+          bool same = true;
+          for (int i : due) same = same && rs[i]->check_size() == msz;
+          bool batched = false;
+          if (same && due.size() > 1 && msz <= 128) {
+            const double te0 = now_s();
+            const size_t mm = (size_t)msz * msz, nd = due.size();
+            double *Aall = static_cast<double *>(ctx->buf("bat_eig").ensure(
+                sizeof(double) * (3 * mm + msz) * nd));
+            double *V0all = Aall + mm * nd, *Vall = V0all + mm * nd, *wall = Vall + mm * nd;
+            for (size_t k = 0; k < nd; ++k) rs[due[k]]->check_prepare(Aall + k * mm, V0all + k * mm);
+            batched = sym_eig_batched(st, msz, (int)nd, Aall, V0all, wall, Vall);
+            if (batched) {
+              PF_HIP(hipStreamSynchronize(st));
+              const double share = (now_s() - te0) / nd;
+              for (size_t k = 0; k < nd; ++k) {
+                rs[due[k]]->t_eig += share;
+                rs[due[k]]->check_finish(wall + k * msz, Vall + k * mm);
+              }
+            }
+          }
+          if (!batched)
+            for (int i : due) rs[i]->check_single();
+        }
       }
     } catch (...) {
       if (graph) (void)hipGraphExecDestroy(graph);
