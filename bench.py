@@ -157,7 +157,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3_fp64", "c3_fp32", "c4"])
     ap.add_argument("--shape", default="",
-                    help="step shape threads,lpl,wg_per_cu,lds_tables,early_loads (else the "
+                    help="step shape threads,lpl,wg_per_cu,lds_tables,early_loads[,rank_incremental] (else the "
                          "profiled one, else tuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -197,6 +197,13 @@ def main():
             autotune.tune_shape(ctx, c, wl.block, prec)
         if prec == 0 and not args.no_fp32:
             autotune.tune_shape(ctx, c, wl.block, 1)
+    form_times = None
+    if wl.block > 0 and len(models) == 1:
+        # Clenshaw or the forward recurrence: one filter of the tuning order
+        # timed both ways with the shape in force; the faster is kept
+        form, secs = autotune.tune_form(ctx, c, wl.block, prec)
+        form_times = {"chosen": "forward" if form == pf.FORM_FORWARD else "clenshaw",
+                      "clenshaw_s": secs[pf.FORM_CLENSHAW], "forward_s": secs[pf.FORM_FORWARD]}
     tune_s = time.perf_counter() - t0
     if wl.block == 0:  # a workload without a fixed block size is autotuned
         t0 = time.perf_counter()
@@ -257,6 +264,7 @@ def main():
                    "K": last["K"] if len(models) == 1 else [min(i["K"] for i in infos), max(i["K"] for i in infos)],
                    "lanczos_blocks": last["m"] if len(models) == 1 else [min(i["m"] for i in infos), max(i["m"] for i in infos)],
                    "precision": wl.precision, "autotune_s": tune_s,
+                   "filter_form": form_times,
                    "step_shape": (list(ctx.get_step_shape(c.L, wl.block, prec))
                                   if wl.block > 0 else None)},
         "time_to_nev_s": wall / args.steps,

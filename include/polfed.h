@@ -160,8 +160,10 @@ int polfed_diag(polfed_ctx *ctx, const polfed_model *model, double *d);
 int polfed_apply_h(polfed_ctx *ctx, const polfed_model *model, int precision,
                    int nvec, const void *X, void *Y);
 /* Y = P^K_sigma(H~) X, with H~ built from E0, E1 (used as given), by the
- * Clenshaw recurrence (Supplement, "Technical details"); precision 0:
- * double, 1: float; K >= 0.  X and Y must not overlap. */
+ * Clenshaw recurrence (Supplement, "Technical details") or by the forward
+ * recurrence that accumulates c_k T_k(H~) X term by term, as the context's
+ * polfed_set_filter_form says; precision 0: double, 1: float; K >= 0.
+ * X and Y must not overlap. */
 int polfed_apply_filter(polfed_ctx *ctx, const polfed_model *model, double E0,
                         double E1, double sigma_tilde, long long K,
                         int precision, int nvec, const void *X, void *Y);
@@ -200,17 +202,23 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *model, int steps,
  * block width nvec (power of two, 1..64) and precision (0: FP64, 1: FP32):
  * threads per workgroup (256 or 1024), 16-byte loads per lane per gathered
  * row (lpl: 1, 2 or 4), persistent workgroups per compute unit (1..32),
- * whether the rank tables are staged in LDS (ignored for L > 26), and
- * whether the streamed operands are loaded before the neighbour gathers
- * (early_loads != 0; results are identical either way).  Entries live in the
- * context; without one the library's built-in default is used.  The
- * autotuner (paper_2005_09534_amd/autotune.py) searches this space. */
+ * whether the rank tables are staged in LDS (ignored for L > 26), whether
+ * the streamed operands are loaded before the neighbour gathers
+ * (early_loads != 0), and how neighbour ranks are found (rank_incremental
+ * = 0: the two rank tables for every bond; != 0: from the row's own rank
+ * by a binomial step for bonds that do not wrap round the chain, the
+ * tables for the rest; the batched solve always uses the tables).  Results
+ * are identical for every shape.  Entries live in the context; without one
+ * the library's built-in default is used.  The autotuner
+ * (paper_2005_09534_amd/autotune.py) searches this space. */
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads,
-                          int lpl, int wg_per_cu, int lds_tables, int early_loads);
+                          int lpl, int wg_per_cu, int lds_tables, int early_loads,
+                          int rank_incremental);
 /* The step shape in force for (L, nvec, precision): the context's entry,
  * else the built-in default.  Outputs as in polfed_set_step_shape. */
 int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads,
-                          int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads);
+                          int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads,
+                          int *rank_incremental);
 /* Block size used when opts->block_size is 0 for chains of length L at the
  * given precision and N_ev (the autotuner's choice); without an entry a
  * built-in rule is used (about N_ev/4, capped at 16 in FP64 and 32 in FP32,
@@ -222,6 +230,16 @@ int polfed_set_block_size(polfed_ctx *ctx, int L, int precision, int nev, int bl
  * where a step is short (blocks up to 64 MB, K <= 2^17).  Results are
  * identical either way. */
 int polfed_set_graphs(polfed_ctx *ctx, int on);
+/* Recurrence that evaluates the filter sum_k c_k T_k(H~) X / D (eq.
+ * (polyTransf)) in polfed_apply_filter and in polfed_solve (its Lanczos
+ * blocks and FP64 refinement): POLFED_FORM_CLENSHAW (the default; Clenshaw's
+ * backward recurrence, Supplement, "Technical details") or
+ * POLFED_FORM_FORWARD (t_{k+1} = 2 H~ t_k - t_{k-1}, with c_k/D times each
+ * t_k added to Y in the same launch; two more streamed blocks per step).
+ * The two agree to rounding.  polfed_solve_batch always uses Clenshaw. */
+#define POLFED_FORM_CLENSHAW 0
+#define POLFED_FORM_FORWARD 1
+int polfed_set_filter_form(polfed_ctx *ctx, int form);
 /* Filter counters accumulated by the context since the last reset (or the
  * start of the last polfed_solve): kernel time of the Chebyshev steps by HIP
  * events on the context's stream (seconds), step launches, and algorithmic

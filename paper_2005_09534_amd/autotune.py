@@ -4,11 +4,15 @@ Two choices are tuned, both through the C ABI of libpolfed:
 
 * the launch shape of the fused Chebyshev-step kernel (threads per group,
   16-byte loads per lane, persistent groups per CU, rank tables in LDS,
-  streamed loads before or after the neighbour gathers) for a
-  (chain length L, block width, precision): each candidate applies the
-  filter for a few dozen steps to a random block of the chain and is timed
-  with the library's HIP-event counters; the fastest shape per HBM-second
-  wins (``polfed_set_step_shape``);
+  streamed loads before or after the neighbour gathers, neighbour ranks from
+  the tables or incrementally) for a (chain length L, block width,
+  precision): each candidate applies the filter for a few dozen steps to a
+  random block of the chain and is timed with the library's HIP-event
+  counters; the fastest shape per HBM-second wins
+  (``polfed_set_step_shape``);
+* the filter recurrence (Clenshaw or the forward form, ``tune_form``): the
+  same filter applied both ways, the shorter time wins
+  (``polfed_set_filter_form``);
 * the Lanczos block size for (L, precision, N_ev): a sample of realisations
   (one, or a batch of a few of the same L) is solved with each candidate
   width and the shortest time to N_ev per realisation wins
@@ -25,9 +29,9 @@ import os
 import time
 
 # (threads, 16-byte loads per lane, groups per CU, LDS rank tables, streamed
-# loads issued before the gathers)
-SHAPES = [(t, lpl, wpc, lds, early) for t, lpl, wpc, lds, early in
-          itertools.product((256, 1024), (1, 2, 4), (1, 2, 4, 8, 16), (1, 0), (0, 1))
+# loads issued before the gathers, incremental neighbour ranks)
+SHAPES = [(t, lpl, wpc, lds, early, ranki) for t, lpl, wpc, lds, early, ranki in
+          itertools.product((256, 1024), (1, 2, 4), (1, 2, 4, 8, 16), (1, 0), (0, 1), (0, 1))
           if not (t == 1024 and wpc > 2)]
 
 
@@ -95,6 +99,34 @@ def tune_shape(ctx, chain, width, precision, steps=None, shapes=SHAPES, cache=No
     return best
 
 
+def tune_form(ctx, chain, width, precision, K=None, margin=0.03):
+    """Filter recurrence with the shorter time for one filter application of
+    order K on this chain and width (step shape as set).  Clenshaw is kept
+    unless the forward form is faster by more than `margin`.  Leaves the
+    choice set on ctx; returns (form, {form: seconds})."""
+    import torch
+    from . import polfed as pf
+    m = pf.make_model(chain.L, chain.J1, chain.J2, chain.Delta, chain.h)
+    n = pf.dim(chain.L)
+    dt = torch.float32 if precision else torch.float64
+    X = torch.randn((n, width), device="cuda", dtype=torch.float64).to(dt)
+    Y = torch.empty_like(X)
+    if K is None:
+        K = max(8, min(200, int(2e9 / (n * width * (4 if precision else 8) * 4))))
+    E0, E1 = -2.0 * chain.L, 2.0 * chain.L
+    secs = {}
+    for form in (pf.FORM_CLENSHAW, pf.FORM_FORWARD):
+        ctx.set_filter_form(form)
+        ctx.apply_filter(m, E0, E1, 0.0, K, X, out=Y)  # warm (graph capture)
+        ctx.filter_stats(reset=True)
+        ctx.apply_filter(m, E0, E1, 0.0, K, X, out=Y)
+        secs[form] = ctx.filter_stats(reset=True)["gpu_s"]
+    form = (pf.FORM_FORWARD if secs[pf.FORM_FORWARD] * (1.0 + margin) < secs[pf.FORM_CLENSHAW]
+            else pf.FORM_CLENSHAW)
+    ctx.set_filter_form(form)
+    return form, secs
+
+
 def tune_block(ctx, chains, nev, precision, widths=(4, 8, 16, 32), cache=None, shape_cache=None):
     """Block size with the shortest time to nev per realisation.
 
@@ -154,6 +186,10 @@ def apply_cache(ctx, cache):
     for k, v in cache.items():
         kind, L, _j2, prec, x = k.split(":")
         if kind == "shape":
-            ctx.set_step_shape(int(L), int(x), int(prec), *[int(t) for t in v[:5]])
+            # entries are the shape followed by its GB/s; older ones lack the
+            # rank-mode field (tables then)
+            sh = [int(t) for t in v[:-1]]
+            sh = (sh + [0])[:6] if len(sh) < 6 else sh[:6]
+            ctx.set_step_shape(int(L), int(x), int(prec), *sh)
         elif kind == "block":
             ctx.set_block_size(int(L), int(prec), int(x), int(v[0]))

@@ -74,6 +74,11 @@ __global__ void k_rank(const uint32_t *states, int32_t *ranks, long long n, cons
   ranks[i] = ok ? tabA[s >> half] + tabB[s & ((1u << half) - 1u)] : -1;
 }
 
+__global__ void k_binom_table(int32_t *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 32 * 32) out[i] = (int32_t)c_binom[i >> 5][i & 31];  // C(31, k) < 2^31
+}
+
 void build_basis(hipStream_t st, Basis &b, int L) {
   b.L = L;
   b.half = L / 2;
@@ -87,6 +92,9 @@ void build_basis(hipStream_t st, Basis &b, int L) {
   k_rank_tables<<<(unsigned)(((1 << b.half) + th - 1) / th), th, 0, st>>>(
       b.tabA.as<int32_t>(), b.tabB.as<int32_t>(), L, b.half);
   check_launch("k_rank_tables");
+  b.binom.ensure(sizeof(int32_t) * 32 * 32);
+  k_binom_table<<<4, 256, 0, st>>>(b.binom.as<int32_t>());
+  check_launch("k_binom_table");
 }
 
 void launch_rank(hipStream_t st, const Basis &b, long long n, const uint32_t *states,

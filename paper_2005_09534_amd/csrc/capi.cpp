@@ -335,7 +335,7 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *m, int steps, unsigned lo
 }
 
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads, int lpl,
-                          int wg_per_cu, int lds_tables, int early_loads) {
+                          int wg_per_cu, int lds_tables, int early_loads, int rank_incremental) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
     PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
@@ -349,18 +349,21 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
     sh.wg_per_cu = wg_per_cu;
     sh.lds_tables = lds_tables ? 1 : 0;
     sh.early_loads = early_loads ? 1 : 0;
+    sh.rank_incr = rank_incremental ? 1 : 0;
     ctx->shapes[std::make_tuple(L, nvec, precision ? 4 : 8)] = sh;
     return POLFED_OK;
   });
 }
 
 int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads, int *lpl,
-                          int *wg_per_cu, int *lds_tables, int *early_loads) {
+                          int *wg_per_cu, int *lds_tables, int *early_loads,
+                          int *rank_incremental) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
     PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
     PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
-    PF_REQUIRE(threads && lpl && wg_per_cu && lds_tables && early_loads, "NULL output");
+    PF_REQUIRE(threads && lpl && wg_per_cu && lds_tables && early_loads && rank_incremental,
+               "NULL output");
     auto it = ctx->shapes.find(std::make_tuple(L, nvec, precision ? 4 : 8));
     const StepShape sh = (it != ctx->shapes.end()) ? it->second : default_shape(L, nvec, precision != 0);
     *threads = sh.threads;
@@ -368,6 +371,7 @@ int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *
     *wg_per_cu = sh.wg_per_cu;
     *lds_tables = sh.lds_tables;
     *early_loads = sh.early_loads;
+    *rank_incremental = sh.rank_incr;
     return POLFED_OK;
   });
 }
@@ -386,6 +390,15 @@ int polfed_set_block_size(polfed_ctx *ctx, int L, int precision, int nev, int bl
 int polfed_set_graphs(polfed_ctx *ctx, int on) {
   return guarded(ctx, [&] {
     ctx->use_graphs = on ? 1 : 0;
+    return POLFED_OK;
+  });
+}
+
+int polfed_set_filter_form(polfed_ctx *ctx, int form) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(form == POLFED_FORM_CLENSHAW || form == POLFED_FORM_FORWARD,
+               "form must be POLFED_FORM_CLENSHAW or POLFED_FORM_FORWARD");
+    ctx->filter_form = form;
     return POLFED_OK;
   });
 }

@@ -23,7 +23,20 @@
 // step (see the tile schedule below), which keeps the gathers of a row's
 // own bit segment inside that XCD's L2.  The rank tables are staged in LDS
 // once per workgroup.
+//
+// Ranks of neighbours come from the two tables, or (RANKI) incrementally
+// from the row's own rank: in the colex rank sum_t C(p_t, t), moving the
+// particle with q particles below it from bit i to bit i+1 adds C(i, q)
+// (Pascal's rule on its one term); a hop from i to i+2 adds C(i, q) +
+// C(i+1, q + n_{i+1}) (two such moves, the second one over or past the
+// particle at i+1); the reverse moves subtract the same.  Bonds that wrap
+// round the chain renumber every particle and take the tables.
+//
+// The forward three-term form t_{k+1} = 2 H~ t_k - t_{k-1} (the sum of
+// c_k T_k(H~) X accumulated term by term) is this kernel with W = t_{k-1}
+// and the fused accumulation acc = cin src + cacc out.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -89,10 +102,11 @@ struct Chunk {
 
 // One row of the fused step: out[r,:] for the lanes (col .. col+VEC) this
 // thread owns.  tA / tB are the rank tables (LDS or global).
-template <class T, int S, int LPL, bool EARLY>
+template <class T, int S, int LPL, bool EARLY, bool RANKI>
 __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int col,
                                          const int32_t *__restrict__ tA,
-                                         const int32_t *__restrict__ tB) {
+                                         const int32_t *__restrict__ tB,
+                                         const int32_t *__restrict__ tC) {
   using C = StepCfg<T, S, LPL>;
   constexpr int VEC = C::VEC, LDV = C::LDV;
   constexpr int kChunk = Chunk<VEC>::value;
@@ -146,8 +160,15 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
           const int i = bit & 31;
           int j = i + l;
           if (j >= L) j -= L;
-          const uint32_t f = s ^ ((1u << i) | (1u << j));
-          idx[u] = tA[f >> half] + tB[f & lomask];
+          if (RANKI && j > i) {
+            const int q = __popc(s & ((1u << i) - 1u));
+            int d = tC[32 * i + q];
+            if (l == 2) d += tC[32 * (i + 1) + q + (int)((s >> (i + 1)) & 1u)];
+            idx[u] = ((s >> i) & 1u) ? (int32_t)r + d : (int32_t)r - d;
+          } else {
+            const uint32_t f = s ^ ((1u << i) | (1u << j));
+            idx[u] = tA[f >> half] + tB[f & lomask];
+          }
           two[u] = (l == 2);
         }
       }
@@ -192,25 +213,37 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] += a.gamma * w[e];
   }
-  store_row_nt<T, VEC, LDV>(a.out + (size_t)r * a.ldo + col, acc);
+  if (!a.skip_out) store_row_nt<T, VEC, LDV>(a.out + (size_t)r * a.ldo + col, acc);
+  if (a.acc != nullptr) {
+    T src[VEC];
+    load_row_nt<T, VEC, LDV>(a.src + (size_t)r * a.ldsrc + col, src);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) src[e] = a.cin * src[e] + a.cacc * acc[e];
+    store_row_nt<T, VEC, LDV>(a.acc + (size_t)r * a.ldacc + col, src);
+  }
 }
 
 // Stage the two rank tables in LDS (when LDS_TAB) and return their bases.
-template <bool LDS_TAB>
-__device__ __forceinline__ void stage_tables(const int32_t *gA, const int32_t *gB, int half,
-                                             int32_t *s_tab, const int32_t *&tA,
-                                             const int32_t *&tB) {
+template <bool LDS_TAB, bool RANKI>
+__device__ __forceinline__ void stage_tables(const int32_t *gA, const int32_t *gB,
+                                             const int32_t *gC, int half, int32_t *s_tab,
+                                             const int32_t *&tA, const int32_t *&tB,
+                                             const int32_t *&tC) {
   tA = gA;
   tB = gB;
+  tC = gC;
   if (LDS_TAB) {
     const int tsz = 1 << half;
     for (int i = threadIdx.x; i < tsz; i += blockDim.x) {
       s_tab[i] = gA[i];
       s_tab[tsz + i] = gB[i];
     }
+    if (RANKI)
+      for (int i = threadIdx.x; i < 32 * 32; i += blockDim.x) s_tab[2 * tsz + i] = gC[i];
     __syncthreads();
     tA = s_tab;
     tB = s_tab + tsz;
+    if (RANKI) tC = s_tab + 2 * tsz;
   }
 }
 
@@ -238,13 +271,13 @@ __device__ __forceinline__ void xcd_tiles(long long ntiles, long long &t_begin, 
   }
 }
 
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY>
+template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
 __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
   using C = StepCfg<T, S, LPL>;
   constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
   extern __shared__ int32_t s_tab[];
-  const int32_t *tA, *tB;
-  stage_tables<LDS_TAB>(a.tabA, a.tabB, a.half, s_tab, tA, tB);
+  const int32_t *tA, *tB, *tC;
+  stage_tables<LDS_TAB, RANKI>(a.tabA, a.tabB, a.binom, a.half, s_tab, tA, tB, tC);
 
   const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
   const long long ntiles = (a.n + rows_per_iter - 1) / rows_per_iter;
@@ -257,7 +290,7 @@ __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
   for (long long t = t_begin; t < t_end; t += t_step) {
     const long long r = t * rows_per_iter + (long long)wave * RPW + slot;
     if (r >= a.n) continue;
-    step_row<T, S, LPL, EARLY>(a, r, col, tA, tB);
+    step_row<T, S, LPL, EARLY, RANKI>(a, r, col, tA, tB, tC);
   }
 }
 
@@ -274,8 +307,8 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
   using C = StepCfg<T, S, LPL>;
   constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
   extern __shared__ int32_t s_tab[];
-  const int32_t *tA, *tB;
-  stage_tables<LDS_TAB>(base.tabA, base.tabB, base.half, s_tab, tA, tB);
+  const int32_t *tA, *tB, *tC;
+  stage_tables<LDS_TAB, false>(base.tabA, base.tabB, base.binom, base.half, s_tab, tA, tB, tC);
 
   const long long n = base.n;
   const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
@@ -321,25 +354,39 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
       a.w2 = (T)(0.5 * (double)it.w2 * it.Dinv);
       a.gamma = (T)(-it.Dinv);
     }
-    step_row<T, S, LPL, EARLY>(a, r, col, tA, tB);
+    step_row<T, S, LPL, EARLY, false>(a, r, col, tA, tB, tC);
   }
 }
 
-// Calls f.template operator()<LDS_TAB, MAXT, EARLY>() for the runtime choice.
-template <class F>
-static void dispatch_shape(bool lds, int threads, bool early, F &&f) {
+// Calls f.template operator()<LDS_TAB, MAXT, EARLY, RANKI>() for the
+// runtime choice (RANKI only where the launcher uses it).
+template <bool RANKI_USED, class F>
+static void dispatch_shape(bool lds, int threads, bool early, bool ranki, F &&f) {
   if (threads != 256 && threads != 1024)
     throw Error(POLFED_EINVAL, "step kernel: threads must be 256 or 1024");
+  auto with_rank = [&](auto lds_c, auto thr_c, auto early_c) {
+    constexpr bool LD = decltype(lds_c)::value;
+    constexpr int TH = decltype(thr_c)::value;
+    constexpr bool EA = decltype(early_c)::value;
+    if (RANKI_USED && ranki)
+      f.template operator()<LD, TH, EA, RANKI_USED>();
+    else
+      f.template operator()<LD, TH, EA, false>();
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  using I256 = std::integral_constant<int, 256>;
+  using I1024 = std::integral_constant<int, 1024>;
   if (threads == 1024) {
     if (lds)
-      early ? f.template operator()<true, 1024, true>() : f.template operator()<true, 1024, false>();
+      early ? with_rank(T_{}, I1024{}, T_{}) : with_rank(T_{}, I1024{}, F_{});
     else
-      early ? f.template operator()<false, 1024, true>() : f.template operator()<false, 1024, false>();
+      early ? with_rank(F_{}, I1024{}, T_{}) : with_rank(F_{}, I1024{}, F_{});
   } else {
     if (lds)
-      early ? f.template operator()<true, 256, true>() : f.template operator()<true, 256, false>();
+      early ? with_rank(T_{}, I256{}, T_{}) : with_rank(T_{}, I256{}, F_{});
     else
-      early ? f.template operator()<false, 256, true>() : f.template operator()<false, 256, false>();
+      early ? with_rank(F_{}, I256{}, T_{}) : with_rank(F_{}, I256{}, F_{});
   }
 }
 
@@ -352,9 +399,16 @@ struct StepLaunch {
   long long nwg;
   int threads;
   size_t shm;
-  template <bool LDS_TAB, int MAXT, bool EARLY>
+  template <bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
   void operator()() const {
-    k_step<T, S, LPL, LDS_TAB, MAXT, EARLY><<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a);
+    // L = 26 tables (64 KB) plus the binomials exceed the default 64 KB of
+    // dynamic LDS per group
+    if (LDS_TAB && shm > 65536)
+      PF_HIP(hipFuncSetAttribute(
+          reinterpret_cast<const void *>(k_step<T, S, LPL, LDS_TAB, MAXT, EARLY, RANKI>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    k_step<T, S, LPL, LDS_TAB, MAXT, EARLY, RANKI>
+        <<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a);
   }
 };
 
@@ -367,7 +421,7 @@ struct BatchedLaunch {
   long long j, Kmax, nwg;
   int threads;
   size_t shm;
-  template <bool LDS_TAB, int MAXT, bool EARLY>
+  template <bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
   void operator()() const {
     k_step_batched<T, S, LPL, LDS_TAB, MAXT, EARLY>
         <<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a, items, B, j, Kmax);
@@ -389,9 +443,11 @@ static void launch_step_s(hipStream_t st, const StepArgs<T> &a0, const StepShape
   nwg = ((nwg + 7) / 8) * 8;
   a.rows_per_wg = rows_per_iter;
   const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
-  const size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
-  dispatch_shape(lds, threads, shape.early_loads != 0,
-                 StepLaunch<T, S, LPL>{st, a, nwg, threads, shm});
+  const bool ranki = shape.rank_incr != 0;
+  const size_t shm =
+      lds ? sizeof(int32_t) * ((size_t)2 * ((size_t)1 << a.half) + (ranki ? 32 * 32 : 0)) : 0;
+  dispatch_shape<true>(lds, threads, shape.early_loads != 0, ranki,
+                       StepLaunch<T, S, LPL>{st, a, nwg, threads, shm});
   check_launch("k_step");
 }
 
@@ -407,8 +463,8 @@ static void launch_batched_s(hipStream_t st, const StepArgs<T> &a, const BatchIt
   nwg = ((nwg + 7) / 8) * 8;
   const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
   const size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
-  dispatch_shape(lds, threads, shape.early_loads != 0,
-                 BatchedLaunch<T, S, LPL>{st, a, items, B, j, Kmax, nwg, threads, shm});
+  dispatch_shape<false>(lds, threads, shape.early_loads != 0, false,
+                        BatchedLaunch<T, S, LPL>{st, a, items, B, j, Kmax, nwg, threads, shm});
   check_launch("k_step_batched");
 }
 

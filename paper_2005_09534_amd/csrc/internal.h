@@ -66,6 +66,7 @@ struct Basis {
   int half = 0;
   long long n = 0;
   DevBuf states, tabA, tabB;
+  DevBuf binom;  // int32 C(n, k) at [32 n + k], n, k < 32
 };
 
 // One chain (model + basis + diagonal in FP64).
@@ -116,6 +117,15 @@ struct StepArgs {
   uint32_t lomask, fullmask;
   int has_j2;
   long long rows_per_wg;
+  const int32_t *binom;  // C(n, k) at [32 n + k] (incremental ranks)
+  // optional fused accumulation (forward recurrence):
+  //   acc[r,:] = cin * src[r,:] + cacc * out[r,:]   (src may be acc itself)
+  T *acc;
+  long long ldacc;
+  const T *src;
+  long long ldsrc;
+  T cin, cacc;
+  int skip_out;  // the step's own output is not stored (only acc is)
 };
 
 // Launch shape of the step kernel (the autotuner's search space).
@@ -125,6 +135,7 @@ struct StepShape {
   int wg_per_cu = 8;     // persistent workgroups per CU
   int lds_tables = 1;    // stage rank tables in LDS
   int early_loads = 0;   // issue the streamed loads before the gathers
+  int rank_incr = 0;     // incremental ranks for bonds that do not wrap
 };
 
 template <class T>
@@ -264,6 +275,7 @@ struct polfed_ctx {
   hipGraphExec_t filter_graph = nullptr;
   std::vector<unsigned long long> filter_graph_key;
   int use_graphs = 1;
+  int filter_form = 0;  // POLFED_FORM_CLENSHAW or POLFED_FORM_FORWARD
   polfed::DevBuf &buf(const std::string &name) {
     auto &p = bufs[name];
     if (!p) p.reset(new polfed::DevBuf());

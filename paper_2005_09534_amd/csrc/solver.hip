@@ -61,7 +61,18 @@ static StepArgs<T> base_args(const Chain &c, const T *dt) {
   a.lomask = (1u << b.half) - 1u;
   a.fullmask = (c.L >= 32) ? 0xffffffffu : ((1u << c.L) - 1u);
   a.has_j2 = (c.J2 != 0.0) ? 1 : 0;
+  a.binom = b.binom.as<int32_t>();
   return a;
+}
+
+// Algorithmic bytes of one step launch: each streamed block once (out, the
+// gathered V, W, X, and the accumulator's source and destination), plus the
+// state word and diagonal of every row when H~ is applied.
+template <class T>
+static double step_bytes(const StepArgs<T> &st, int S) {
+  const int streams = (st.skip_out ? 0 : 1) + (st.V ? 1 : 0) + (st.W ? 1 : 0) +
+                      (st.X ? 1 : 0) + (st.acc ? 2 : 0);
+  return (double)st.n * (S * (double)sizeof(T) * streams + (st.V ? 4.0 + sizeof(T) : 0.0));
 }
 
 static StepShape shape_for(const polfed_ctx *ctx, int L, int S, bool fp32) {
@@ -93,17 +104,97 @@ static void apply_op(polfed_ctx *ctx, const Chain &c, const T *dt, double wscale
   }
 }
 
+// Y = P^K_sigma(H~) X = (sum_k c_k T_k(H~) X) / D by the forward three-term
+// recurrence: t_0 = X, t_1 = H~ X, t_{k+1} = 2 H~ t_k - t_{k-1}, each t_k
+// added to Y with weight c_k / D as it is made (steps after the last
+// non-zero c_k are not run).  Returns the algorithmic bytes of the launches;
+// with launch = false only counts them.
+template <class T>
+static double queue_filter_forward(hipStream_t stream, int num_cu, const StepShape &shape,
+                                   const Chain &c, const T *dt, double a, int S, const T *X,
+                                   long long ldx, T *Y, long long ldy, long long K,
+                                   const std::vector<double> &coef, double D, T *buf3,
+                                   bool launch) {
+  const long long n = c.basis->n;
+  T *bufs[3] = {buf3, buf3 + (size_t)n * S, buf3 + (size_t)2 * n * S};
+  const double Dinv = 1.0 / D;
+  double moved = 0.0;
+  long long klast = 0;
+  for (long long k = K; k >= 1; --k)
+    if (coef[k] != 0.0) {
+      klast = k;
+      break;
+    }
+  if (klast == 0) {  // Y = c_0 X / D
+    StepArgs<T> st = base_args<T>(c, dt);
+    st.out = Y;
+    st.ldo = ldy;
+    st.X = X;
+    st.ldx = ldx;
+    st.alpha = (T)(coef[0] * Dinv);
+    if (launch) launch_step<T>(stream, S, st, shape, num_cu);
+    return step_bytes(st, S);
+  }
+  for (long long k = 1; k <= klast; ++k) {
+    StepArgs<T> st = base_args<T>(c, dt);
+    st.out = bufs[(k - 1) % 3];
+    st.ldo = S;
+    st.skip_out = (k == klast) ? 1 : 0;
+    if (k == 1) {  // t_1 = H~ X
+      st.V = X;
+      st.ldv = ldx;
+      st.dscale = T(1);
+      st.w1 = (T)(0.5 * a * c.J1);
+      st.w2 = (T)(0.5 * a * c.J2);
+      st.acc = Y;
+      st.ldacc = ldy;
+      st.src = X;
+      st.ldsrc = ldx;
+      st.cin = (T)(coef[0] * Dinv);
+      st.cacc = (T)(coef[1] * Dinv);
+    } else {  // t_k = 2 H~ t_{k-1} - t_{k-2}
+      st.V = bufs[(k - 2) % 3];
+      st.ldv = S;
+      if (k == 2) {
+        st.W = X;
+        st.ldw = ldx;
+      } else {
+        st.W = bufs[(k - 3) % 3];
+        st.ldw = S;
+      }
+      st.dscale = T(2);
+      st.w1 = (T)(a * c.J1);
+      st.w2 = (T)(a * c.J2);
+      st.gamma = T(-1);
+      if (coef[k] != 0.0) {
+        st.acc = Y;
+        st.ldacc = ldy;
+        st.src = Y;
+        st.ldsrc = ldy;
+        st.cin = T(1);
+        st.cacc = (T)(coef[k] * Dinv);
+      }
+    }
+    if (launch) launch_step<T>(stream, S, st, shape, num_cu);
+    moved += step_bytes(st, S);
+  }
+  return moved;
+}
+
 // Y = P^K_sigma(H~) X by Clenshaw:  b_k = c_k X + 2 H~ b_{k+1} - b_{k+2},
-// k = K..1, then Y = (c_0 X + H~ b_1 - b_2) / D.  dt = a d + b in T.
-// Returns the algorithmic bytes of the launches it queues.
+// k = K..1, then Y = (c_0 X + H~ b_1 - b_2) / D (or by the forward form,
+// per `form`).  dt = a d + b in T.  Returns the algorithmic bytes of the
+// launches it queues; with launch = false only counts them.
 template <class T>
 static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shape, const Chain &c,
                            const T *dt, double a, int S, const T *X, long long ldx, T *Y,
                            long long ldy, long long K, const std::vector<double> &coef, double D,
-                           T *buf3) {
+                           T *buf3, int form, bool launch = true) {
+  if (form == POLFED_FORM_FORWARD)
+    return queue_filter_forward<T>(stream, num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
+                                   D, buf3, launch);
   const long long n = c.basis->n;
   T *bufs[3] = {buf3, buf3 + (size_t)n * S, buf3 + (size_t)2 * n * S};
-  const double bpv = sizeof(T);
   double moved = 0.0;
   for (long long j = 0; j < K; ++j) {
     const long long k = K - j;
@@ -127,9 +218,8 @@ static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shap
     st.w1 = (T)(a * c.J1);
     st.w2 = (T)(a * c.J2);
     st.gamma = T(-1);
-    launch_step<T>(stream, S, st, shape, num_cu);
-    const int streams = 1 + (st.V ? 1 : 0) + (st.W ? 1 : 0) + (st.X ? 1 : 0);
-    moved += (double)n * (S * bpv * streams + (st.V ? 4.0 + bpv : 0.0));
+    if (launch) launch_step<T>(stream, S, st, shape, num_cu);
+    moved += step_bytes(st, S);
   }
   StepArgs<T> st = base_args<T>(c, dt);
   st.out = Y;
@@ -151,9 +241,8 @@ static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shap
   st.w1 = (T)(0.5 * (a * c.J1) * Dinv);
   st.w2 = (T)(0.5 * (a * c.J2) * Dinv);
   st.gamma = (T)(-Dinv);
-  launch_step<T>(stream, S, st, shape, num_cu);
-  const int streams = 2 + (st.V ? 1 : 0) + (st.W ? 1 : 0);
-  moved += (double)n * (S * bpv * streams + (st.V ? 4.0 + bpv : 0.0));
+  if (launch) launch_step<T>(stream, S, st, shape, num_cu);
+  moved += step_bytes(st, S);
   return moved;
 }
 
@@ -176,17 +265,7 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
     PF_HIP(hipEventCreate(&ctx->ev_stop));
   }
   double moved = 0.0;
-  // algorithmic bytes of the K + 1 steps (same model as queue_filter)
-  auto step_bytes = [&]() {
-    double mv = 0.0;
-    for (long long j = 0; j < K; ++j) {
-      const int streams = 1 + (j >= 1) + (j >= 2) + (coef[K - j] != 0.0);
-      mv += (double)n * (S * (double)sizeof(T) * streams + (j >= 1 ? 4.0 + sizeof(T) : 0.0));
-    }
-    mv += (double)n * (S * (double)sizeof(T) * (2 + (K >= 1) + (K >= 2)) +
-                       (K >= 1 ? 4.0 + sizeof(T) : 0.0));
-    return mv;
-  };
+  const int form = ctx->filter_form;
   // a graph pays for its capture only when it is replayed: filters run once
   // (the refinement passes, each with its own order) launch directly
   if (reused && ctx->use_graphs && graph_worthwhile<T>(n, S, K)) {
@@ -199,7 +278,8 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
         (unsigned long long)(uintptr_t)c.basis->states.p,
         (unsigned long long)shape.threads, (unsigned long long)shape.lpl,
         (unsigned long long)shape.wg_per_cu, (unsigned long long)shape.lds_tables,
-        (unsigned long long)shape.early_loads};
+        (unsigned long long)shape.early_loads, (unsigned long long)shape.rank_incr,
+        (unsigned long long)form};
     auto bits = [](double v) {
       unsigned long long u;
       std::memcpy(&u, &v, sizeof(u));
@@ -226,7 +306,7 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
       PF_HIP(hipStreamBeginCapture(ctx->own_stream, hipStreamCaptureModeThreadLocal));
       try {
         queue_filter<T>(ctx->own_stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
-                        D, buf3);
+                        D, buf3, form);
       } catch (...) {
         hipGraph_t dummy = nullptr;
         (void)hipStreamEndCapture(ctx->own_stream, &dummy);
@@ -242,11 +322,12 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
     PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
     PF_HIP(hipGraphLaunch(ctx->filter_graph, ctx->stream));
     // same byte model as the direct path
-    moved = step_bytes();
+    moved = queue_filter<T>(ctx->own_stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K,
+                            coef, D, buf3, form, false);
   } else {
     PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
     moved = queue_filter<T>(ctx->stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
-                            D, buf3);
+                            D, buf3, form);
   }
   if (bytes) *bytes += moved;
   PF_HIP(hipEventRecord(ctx->ev_stop, ctx->stream));
@@ -254,7 +335,16 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
   float ms = 0.0f;
   PF_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
   ctx->filter_gpu_s += 1e-3 * ms;
-  ctx->filter_launches += (double)(K + 1);
+  long long launches = K + 1;
+  if (form == POLFED_FORM_FORWARD) {  // steps 1 .. last non-zero c_k, at least one
+    launches = 1;
+    for (long long k = K; k >= 1; --k)
+      if (coef[k] != 0.0) {
+        launches = k;
+        break;
+      }
+  }
+  ctx->filter_launches += (double)launches;
   ctx->filter_bytes += moved;
 }
 
@@ -1287,6 +1377,14 @@ int solve_batch(polfed_ctx *ctx, int R, const polfed_model *models, const polfed
                 int *status) {
   polfed_opts o = resolve_opts(opts_in);
   PF_REQUIRE(R >= 1 && models && status && evals && resid, "invalid batch arguments");
+  // the batched kernel is Clenshaw's; the members' single-chain filters (the
+  // refinement) follow it, whatever the context's setting
+  struct FormGuard {
+    polfed_ctx *c;
+    int saved;
+    ~FormGuard() { c->filter_form = saved; }
+  } guard{ctx, ctx->filter_form};
+  ctx->filter_form = POLFED_FORM_CLENSHAW;
   if (o.precision == 1)
     return solve_batch_impl<float>(ctx, R, models, o, nev, evals, evecs, resid, infos, status);
   return solve_batch_impl<double>(ctx, R, models, o, nev, evals, evecs, resid, infos, status);

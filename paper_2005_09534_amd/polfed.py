@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpolfed.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "polfed.h")
 
 OK, NOT_CONVERGED = 0, 1
+FORM_CLENSHAW, FORM_FORWARD = 0, 1
 EINVAL, ENOMEM, EDEVICE, EBOUNDS, EBREAKDOWN = -1, -2, -3, -4, -5
 
 c_int, c_double, c_ll, c_ull, c_void_p = (ctypes.c_int, ctypes.c_double, ctypes.c_longlong,
@@ -95,9 +96,10 @@ def _load():
         "polfed_bounds": (c_int, [c_void_p, ctypes.POINTER(Model), c_int, c_ull, P_double,
                                   P_double, P_double, P_double]),
         "polfed_set_step_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int,
-                                          c_int, c_int]),
-        "polfed_get_step_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 5),
+                                          c_int, c_int, c_int]),
+        "polfed_get_step_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 6),
         "polfed_set_graphs": (c_int, [c_void_p, c_int]),
+        "polfed_set_filter_form": (c_int, [c_void_p, c_int]),
         "polfed_set_block_size": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
         "polfed_filter_stats": (c_int, [c_void_p, P_double, P_double, P_double, c_int]),
         "polfed_solve": (c_int, [c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts), c_int,
@@ -283,13 +285,15 @@ class Context:
 
     # ---- tuning / measurement ----
     def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1,
-                       early_loads=0):
+                       early_loads=0, rank_incremental=0):
         self._check(LIB.polfed_set_step_shape(self.h, L, nvec, precision, threads, lpl, wg_per_cu,
-                                              int(lds_tables), int(early_loads)),
+                                              int(lds_tables), int(early_loads),
+                                              int(rank_incremental)),
                     "set_step_shape")
 
     def get_step_shape(self, L, nvec, precision):
-        out = [c_int() for _ in range(5)]
+        """(threads, lpl, wg_per_cu, lds_tables, early_loads, rank_incremental)."""
+        out = [c_int() for _ in range(6)]
         self._check(LIB.polfed_get_step_shape(self.h, L, nvec, precision,
                                               *[ctypes.byref(o) for o in out]), "get_step_shape")
         return tuple(o.value for o in out)
@@ -300,6 +304,10 @@ class Context:
 
     def set_graphs(self, on):
         self._check(LIB.polfed_set_graphs(self.h, int(bool(on))), "set_graphs")
+
+    def set_filter_form(self, form):
+        """FORM_CLENSHAW (default) or FORM_FORWARD."""
+        self._check(LIB.polfed_set_filter_form(self.h, int(form)), "set_filter_form")
 
     def filter_stats(self, reset=True):
         g, l, b = c_double(), c_double(), c_double()

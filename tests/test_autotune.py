@@ -9,9 +9,10 @@ class _FakeCtx:
     def __init__(self):
         self.calls = []
 
-    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1, early_loads=0):
+    def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1, early_loads=0,
+                       rank_incremental=0):
         self.calls.append(("shape", L, nvec, precision, threads, lpl, wg_per_cu, lds_tables,
-                           early_loads))
+                           early_loads, rank_incremental))
 
     def set_block_size(self, L, precision, nev, block_size):
         self.calls.append(("block", L, precision, nev, block_size))
@@ -19,13 +20,15 @@ class _FakeCtx:
 
 def test_shape_candidates_are_valid():
     assert len(autotune.SHAPES) == len(set(autotune.SHAPES))
-    for t, lpl, wpc, lds, early in autotune.SHAPES:
+    for t, lpl, wpc, lds, early, ranki in autotune.SHAPES:
         assert t in (256, 1024) and lpl in (1, 2, 4) and lds in (0, 1) and early in (0, 1)
-        assert wpc >= 1
+        assert ranki in (0, 1) and wpc >= 1
+    assert {sh[5] for sh in autotune.SHAPES} == {0, 1}
 
 
 def test_cache_round_trip_and_apply(tmp_path):
-    cache = {autotune._key("shape", 18, 0.0, 1, 32): [1024, 2, 2, 1, 0, 2500.0],
+    # the second shape entry is in the older five-field form (no rank mode)
+    cache = {autotune._key("shape", 18, 0.0, 1, 32): [1024, 2, 2, 1, 0, 1, 2500.0],
              autotune._key("block", 18, 0.0, 1, 20): [8, 0.5],
              autotune._key("shape", 22, 1.0, 0, 16): [256, 1, 4, 0, 1, 1800.0]}
     path = tmp_path / "tune.json"
@@ -35,9 +38,9 @@ def test_cache_round_trip_and_apply(tmp_path):
     assert back == cache
     ctx = _FakeCtx()
     autotune.apply_cache(ctx, back)
-    assert sorted(ctx.calls) == sorted([("shape", 18, 32, 1, 1024, 2, 2, 1, 0),
+    assert sorted(ctx.calls) == sorted([("shape", 18, 32, 1, 1024, 2, 2, 1, 0, 1),
                                         ("block", 18, 1, 20, 8),
-                                        ("shape", 22, 16, 0, 256, 1, 4, 0, 1)])
+                                        ("shape", 22, 16, 0, 256, 1, 4, 0, 1, 0)])
 
 
 def test_missing_cache_is_empty(tmp_path):

@@ -22,10 +22,14 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("precision,width", [(0, 8), (1, 32)])
-def test_shapes_bitwise_identical(ctx, precision, width):
+@pytest.mark.parametrize("precision,width,J2", [(0, 8, 0.0), (1, 32, 0.0), (0, 4, 0.6),
+                                                (1, 16, 0.6)])
+def test_shapes_bitwise_identical(ctx, precision, width, J2):
+    """Every launch shape, incremental neighbour ranks included (J2 != 0
+    exercises the two-site hops and both wrap-round bond kinds), gives the
+    same filter bit for bit."""
     from paper_2005_09534_amd import autotune, polfed as pf
-    c = workloads.chain(14, 2.0, 7)
+    c = workloads.chain(14, 2.0, 7, J2=J2)
     m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
     n = pf.dim(c.L)
     dt = torch.float32 if precision else torch.float64
@@ -35,8 +39,9 @@ def test_shapes_bitwise_identical(ctx, precision, width):
     E0w, E1w = E0 - r0 - 1e-3 * w, E1 + r1 + 1e-3 * w
     ref = None
     early = [sh for sh in autotune.SHAPES if sh[4] == 1]
-    assert early
-    for sh in autotune.SHAPES[::3] + early[::2]:
+    ranki = [sh for sh in autotune.SHAPES if sh[5] == 1]
+    assert early and ranki
+    for sh in autotune.SHAPES[::3] + early[::2] + ranki[::5]:
         ctx.set_step_shape(c.L, width, precision, *sh)
         Y = ctx.apply_filter(m, E0w, E1w, 0.0, 40, X)
         torch.cuda.synchronize()
@@ -71,7 +76,7 @@ def test_tune_shape_and_block(ctx):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_early_loads_shape_in_a_solve(ctx, precision):
     """A solve whose step kernel issues the streamed loads before the gathers
-    returns the dense answer."""
+    and ranks neighbours incrementally returns the dense answer."""
     from oracle import chain as ochain, dense
     from paper_2005_09534_amd import polfed as pf
     c = workloads.chain(12, 3.0, 1)
@@ -79,7 +84,7 @@ def test_early_loads_shape_in_a_solve(ctx, precision):
     w = dense.full_spectrum(H)
     normH = max(abs(w[0]), abs(w[-1]))
     m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
-    ctx.set_step_shape(c.L, 4, precision, 256, 1, 2, 1, 1)
+    ctx.set_step_shape(c.L, 4, precision, 256, 1, 2, 1, 1, 1)
     r = ctx.solve(m, 20, block_size=4, precision=precision, vectors=True)
     assert r["status"] == pf.OK
     Ed = w[dense.nearest_from_spectrum(w, r["info"]["sigma_energy"], 20)]
@@ -94,4 +99,6 @@ def test_get_step_shape_reports_what_is_in_force(ctx):
     ctx.set_step_shape(20, 8, 1, *sh)
     assert ctx.get_step_shape(20, 8, 1) == tuple(sh)
     d = ctx.get_step_shape(20, 8, 0)  # untouched entry: the built-in default
-    assert d[0] in (256, 1024) and d[1] in (1, 2, 4) and d[2] >= 1
+    assert len(d) == 6 and d[0] in (256, 1024) and d[1] in (1, 2, 4) and d[2] >= 1
+    ctx.set_step_shape(20, 8, 1, 256, 2, 8)  # trailing fields default to 1, 0, 0
+    assert ctx.get_step_shape(20, 8, 1) == (256, 2, 8, 1, 0, 0)
