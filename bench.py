@@ -272,6 +272,10 @@ def main():
                                        "t_refine", "t_total", "max_resid", "normH", "n_conv",
                                        "refine_passes")},
         "max_resid_rel": max(i["max_resid"] / i["normH"] for i in infos),
+        # FP32 refinement passes per solve (-1: FP64 re-solve after a failed
+        # refinement), as {passes: count}
+        "refine_passes_hist": {str(k): v for k, v in sorted(
+            __import__("collections").Counter(int(i["refine_passes"]) for i in infos).items())},
         "roofline": {
             "kernel": "k_step (fused Chebyshev step: matrix-free H~ gather + 3-term update)",
             "bound": "hbm",
