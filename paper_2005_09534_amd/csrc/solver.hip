@@ -1047,10 +1047,16 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
       PF_HIP(hipStreamSynchronize(st));
       t_refine += now_s() - tr0;
       ++passes;
+      const double rprev = rmax;
       rmax = rayleigh_ritz(q);
       if (verbose)
         fprintf(stderr, "[polfed] refine pass %d: K_r %lld, %d vectors, max resid / ||H|| = %.3e\n",
                 passes, K_r, q, rmax / normH);
+      // a pass at (about) the full order K that gains less than 10% has
+      // stalled (a wanted direction missing from, or barely separated
+      // within, the refined span); more passes would not reach the target,
+      // and the caller's FP64 re-solve is cheaper than running them out
+      if (2 * K_r > K_ref && rmax > 0.9 * rprev) break;
       K_r = std::min<long long>(2 * K_r, K_ref);
     }
   }
