@@ -186,10 +186,23 @@ def column_cap(nwin, s):
     return -(-cols // s) * s
 
 
+MAX_WINDOW_FACTOR = 12.0
+
+
 def solve(L, J1, J2, Delta, h, nev, s, sigma_H=None, eps_target=0.5, K=None,
-          p=0.17, eta=1e-3, tau=1e-10, rng_seed=0, nev_window=None, max_cols=None):
+          p=0.17, eta=1e-3, tau=1e-10, rng_seed=0, nev_window=None, max_cols=None,
+          window_factor=1.5):
     """Full POLFED solve (FP64).  Returns dict(E, V, resid, K, m, sigma_H,
-    E0, E1, sigma_t)."""
+    E0, E1, sigma_t, window_factor).
+
+    Reading: K comes from the Gaussian DOS (main text, "POLFED algorithm"),
+    which can put fewer than N_ev eigenvalues inside the lobe P >= p when the
+    true density at the target is lower (short, strongly disordered chains).
+    Outside the lobe the filter value is no measure of distance from the
+    target, so a run that stops with fewer than N_ev Ritz values at theta >= p
+    is repeated with the window sized for twice as many eigenvalues (K about
+    halves), up to a factor of 12 N_ev.  Only when K is not given."""
+    max_cols_arg = max_cols
     H = chain.hamiltonian_csr(L, J1, J2, Delta, h)
     n = H.shape[0]
     E0, E1 = extreme_eigenvalues(H)
@@ -198,7 +211,8 @@ def solve(L, J1, J2, Delta, h, nev, s, sigma_H=None, eps_target=0.5, K=None,
     E0w, E1w = widened_bounds(E0, E1, eta)
     a, b = chebyshev.rescale_coeffs(E0w, E1w)
     sigma_t = a * sigma_H + b
-    nwin = window_count(nev) if nev_window is None else nev_window
+    nwin = window_count(nev, window_factor) if nev_window is None else nev_window
+    K_auto = K is None
     if K is None:
         Ebar = float(H.diagonal().sum()) / n
         Gamma = chebyshev.dos_gamma(L, J1, J2, Delta, h)
@@ -207,6 +221,11 @@ def solve(L, J1, J2, Delta, h, nev, s, sigma_H=None, eps_target=0.5, K=None,
         max_cols = column_cap(nwin, s)
     res = block_lanczos(H, E0w, E1w, sigma_t, K, nev, s, p=p, tau=tau, rng_seed=rng_seed,
                         max_cols=max_cols)
+    if (K_auto and nev_window is None and int(np.sum(res["theta"] >= p)) < nev
+            and 2.0 * window_factor <= MAX_WINDOW_FACTOR):
+        return solve(L, J1, J2, Delta, h, nev, s, sigma_H=sigma_H, eps_target=eps_target, K=None,
+                     p=p, eta=eta, tau=tau, rng_seed=rng_seed, nev_window=None,
+                     max_cols=max_cols_arg, window_factor=2.0 * window_factor)
     U = res["Qm"] @ res["t"][:, candidates(res["theta"], p, nev)]
     eps, V = rayleigh_ritz(H, U, a, b)
     E = (eps - b) / a
@@ -214,4 +233,5 @@ def solve(L, J1, J2, Delta, h, nev, s, sigma_H=None, eps_target=0.5, K=None,
     V = sign_normalise(V)
     return dict(E=E, V=V, resid=residuals(H, E, V), K=K, m=res["m"], nconv=res["nconv"],
                 sigma_H=sigma_H, E0=E0, E1=E1, E0w=E0w, E1w=E1w, sigma_t=sigma_t, nwin=nwin,
+                window_factor=window_factor,
                 theta=res["theta"], T=res["T"], Qm=res["Qm"])

@@ -468,6 +468,9 @@ static polfed_opts resolve_opts(const polfed_opts *in) {
 // values sit below p where the filter separates them poorly) is recomputed
 // with the FP64 filter; info->refine_passes is then -1.
 constexpr double kFp32ResidBar = 1e-8;
+// Widest filter window (in units of N_ev) the solve grows to when the
+// Gaussian DOS has sized it too narrow: the default 1.5 doubled three times.
+constexpr double kMaxWindowFactor = 12.0;
 
 template <class T>
 struct Realization {
@@ -489,6 +492,7 @@ struct Realization {
   DevBuf Vprevb, thprevb, Wb;
   int ms_prev = 0;
   int m_done = 0, nconv = 0, refills = 0;
+  int above = 0;  // Ritz values with theta >= p at the last convergence check
   bool done = false;
   double t_start = 0, t_bounds = 0, t_filter = 0, t_orth = 0, t_eig = 0, bytes = 0;
   double filter_gpu_s = 0, filter_launches = 0;
@@ -515,6 +519,12 @@ struct Realization {
   void check_finish(const double *th, const double *Vt);
   void check_single();  // prepare, sym_eig, finish
   int finalize(double *evals, double *evecs, double *resid, polfed_info *info);
+  // The filter window held fewer than nev Ritz values with theta >= p at
+  // the last check: the order K from the Gaussian DOS made the main lobe too
+  // narrow for nev eigenvalues (a DOS that is low at the target, as in short
+  // strongly disordered chains), and outside the lobe theta is no measure of
+  // nearness to the target.  Only for an automatic K.
+  bool window_short() const { return o.K <= 0 && above < nev; }
 
  private:
   int cholqr2(double *X, double *out, long long ldo);
@@ -788,7 +798,7 @@ void Realization<T>::check_finish(const double *th, const double *Vt) {
   // Ritz values exceed p (the Gaussian DOS overestimated the window), the
   // nev largest theta take their place
   double thr = o.p;
-  int above = 0;
+  above = 0;
   for (int i = 0; i < ms; ++i) above += theta[i] >= o.p;
   if (above < nev) thr = theta[std::max(0, ms - nev)];  // ascending order
   nconv = 0;
@@ -1118,7 +1128,8 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
 
 template <class T>
 static int solve_single(polfed_ctx *ctx, const polfed_model *model, const polfed_opts &o, int nev,
-                        double *evals, double *evecs, double *resid, polfed_info *info) {
+                        double *evals, double *evecs, double *resid, polfed_info *info,
+                        bool *short_window = nullptr) {
   Realization<T> R;
   R.setup(ctx, model, o, nev);
   T *cheb = static_cast<T *>(ctx->buf("cheb").ensure(sizeof(T) * 3 * (size_t)R.n * R.s));
@@ -1133,17 +1144,14 @@ static int solve_single(polfed_ctx *ctx, const polfed_model *model, const polfed
     R.t_filter += now_s() - t0;
     R.lanczos_step();
   }
+  if (short_window) *short_window = R.window_short();
   return R.finalize(evals, evecs, resid, info);
 }
 
 
-static int fp64_resolve(polfed_ctx *ctx, const polfed_model *model, const polfed_opts &o, int nev,
-                        double *evals, double *evecs, double *resid, polfed_info *info,
-                        const polfed_info &first) {
-  polfed_opts o64 = o;
-  o64.precision = 0;
-  polfed_info i64;
-  const int rc = solve_single<double>(ctx, model, o64, nev, evals, evecs, resid, &i64);
+// Info of an FP64 re-solve (i64) after a failed FP32 attempt (first):
+// refine_passes = -1, and the attempt's time and work added in.
+static void merge_resolve_info(polfed_info &i64, const polfed_info &first) {
   i64.refine_passes = -1;
   i64.t_total += first.t_total;
   i64.t_refine += first.t_total;  // the abandoned FP32 attempt
@@ -1151,23 +1159,63 @@ static int fp64_resolve(polfed_ctx *ctx, const polfed_model *model, const polfed
   i64.filter_bytes += first.filter_bytes;
   i64.filter_gpu_s += first.filter_gpu_s;
   i64.filter_launches += first.filter_launches;
-  if (info) *info = i64;
-  return rc;
+}
+
+// Time and work of an abandoned attempt added to the info of the result.
+static void add_attempt(polfed_info &info, const polfed_info &prev) {
+  info.t_total += prev.t_total;
+  info.hv_apps += prev.hv_apps;
+  info.filter_bytes += prev.filter_bytes;
+  info.filter_gpu_s += prev.filter_gpu_s;
+  info.filter_launches += prev.filter_launches;
+}
+
+// A solve in precision T, repeated with the window sized for twice as many
+// eigenvalues (o.window_factor doubled, so K about halves) while the window
+// turns out too narrow, up to kMaxWindowFactor; a window still too narrow
+// there makes the status NOT_CONVERGED.  o is left at the factor used.
+template <class T>
+static int solve_widened(polfed_ctx *ctx, const polfed_model *model, polfed_opts &o, int nev,
+                         double *evals, double *evecs, double *resid, polfed_info *info) {
+  polfed_info prev;
+  bool have_prev = false;
+  for (;;) {
+    bool short_window = false;
+    int rc = solve_single<T>(ctx, model, o, nev, evals, evecs, resid, info, &short_window);
+    if (have_prev) add_attempt(*info, prev);
+    if (!short_window) return rc;
+    if (2.0 * o.window_factor > kMaxWindowFactor)
+      return rc == POLFED_OK ? POLFED_NOT_CONVERGED : rc;
+    prev = *info;
+    have_prev = true;
+    o.window_factor *= 2.0;
+  }
 }
 
 int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opts_in, int nev,
               double *evals, double *evecs, double *resid, polfed_info *info) {
   polfed_opts o = resolve_opts(opts_in);
   PF_REQUIRE(evals != nullptr && resid != nullptr, "evals and resid must not be NULL");
+  polfed_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  int rc;
   if (o.precision == 1) {
-    polfed_info i32;
-    const int rc = solve_single<float>(ctx, model, o, nev, evals, evecs, resid, &i32);
-    if (i32.max_resid > kFp32ResidBar * i32.normH)
-      return fp64_resolve(ctx, model, o, nev, evals, evecs, resid, info, i32);
-    if (info) *info = i32;
-    return rc;
+    rc = solve_widened<float>(ctx, model, o, nev, evals, evecs, resid, &inf);
+    if (inf.max_resid > kFp32ResidBar * inf.normH) {
+      // the FP32 result misses the bar: recompute with the FP64 filter
+      polfed_opts o64 = o;
+      o64.precision = 0;
+      polfed_info i64;
+      std::memset(&i64, 0, sizeof(i64));
+      rc = solve_widened<double>(ctx, model, o64, nev, evals, evecs, resid, &i64);
+      merge_resolve_info(i64, inf);
+      inf = i64;
+    }
+  } else {
+    rc = solve_widened<double>(ctx, model, o, nev, evals, evecs, resid, &inf);
   }
-  return solve_single<double>(ctx, model, o, nev, evals, evecs, resid, info);
+  if (info) *info = inf;
+  return rc;
 }
 
 // Batched solve: realisations are grouped by chain length (and block size);
@@ -1355,6 +1403,11 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
     PF_HIP(hipEventDestroy(e0));
     PF_HIP(hipEventDestroy(e1));
     const double tg1 = now_s();
+    // members whose window was too narrow, and members whose FP32 result
+    // misses the bar, each with its first attempt
+    std::vector<int> widen, redo;
+    std::vector<polfed_info> first_w, first;
+    const bool can_widen = 2.0 * og.window_factor <= kMaxWindowFactor;
     for (int i = 0; i < B; ++i) {
       const int r = mem[i];
       rs[i]->filter_gpu_s = gfilter / B;
@@ -1362,13 +1415,76 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
       polfed_info ir;
       int rc = rs[i]->finalize(evals + (size_t)r * nev, evecs ? evecs + voff[r] : nullptr,
                                resid + (size_t)r * nev, &ir);
-      if (rs[i]->fp32 && ir.max_resid > kFp32ResidBar * ir.normH)
-        rc = fp64_resolve(ctx, &models[r], og, nev, evals + (size_t)r * nev,
-                          evecs ? evecs + voff[r] : nullptr, resid + (size_t)r * nev, &ir, ir);
+      if (rs[i]->window_short()) {
+        if (can_widen) {
+          widen.push_back(r);
+          first_w.push_back(ir);
+          continue;
+        }
+        if (rc == POLFED_OK) rc = POLFED_NOT_CONVERGED;
+      } else if (rs[i]->fp32 && ir.max_resid > kFp32ResidBar * ir.normH) {
+        redo.push_back(r);
+        first.push_back(ir);
+        continue;
+      }
       if (infos) infos[r] = ir;
       status[r] = rc;
       if (rc > 0 && worst == POLFED_OK) worst = rc;
     }
+    rs.clear();  // the group's device state is no longer needed
+    // a sub-batch of the members `ids` with options `os` (in FP64 when
+    // fp64); results go to their places, each info merged with the member's
+    // first attempt by `merge`
+    auto rerun = [&](const std::vector<int> &ids, const std::vector<polfed_info> &firsts,
+                     const polfed_opts &os, bool fp64, void (*merge)(polfed_info &, const polfed_info &)) {
+      const int nr = (int)ids.size();
+      std::vector<polfed_model> sub(nr);
+      size_t tot = 0;
+      for (int k = 0; k < nr; ++k) {
+        sub[k] = models[ids[k]];
+        tot += (size_t)polfed_dim(sub[k].L) * nev;
+      }
+      std::vector<double> ev((size_t)nr * nev), rsd((size_t)nr * nev);
+      std::vector<double> vv(evecs ? tot : 0);
+      std::vector<polfed_info> inf(nr);
+      std::vector<int> stt(nr);
+      if (fp64)
+        solve_batch_impl<double>(ctx, nr, sub.data(), os, nev, ev.data(),
+                                 evecs ? vv.data() : nullptr, rsd.data(), inf.data(), stt.data());
+      else
+        solve_batch_impl<T>(ctx, nr, sub.data(), os, nev, ev.data(), evecs ? vv.data() : nullptr,
+                            rsd.data(), inf.data(), stt.data());
+      size_t off = 0;
+      for (int k = 0; k < nr; ++k) {
+        const int r = ids[k];
+        const size_t len = (size_t)polfed_dim(sub[k].L) * nev;
+        std::memcpy(evals + (size_t)r * nev, ev.data() + (size_t)k * nev, sizeof(double) * nev);
+        std::memcpy(resid + (size_t)r * nev, rsd.data() + (size_t)k * nev, sizeof(double) * nev);
+        if (evecs) std::memcpy(evecs + voff[r], vv.data() + off, sizeof(double) * len);
+        off += len;
+        polfed_info ir = inf[k];
+        merge(ir, firsts[k]);
+        if (infos) infos[r] = ir;
+        status[r] = stt[k];
+        if (stt[k] > 0 && worst == POLFED_OK) worst = stt[k];
+      }
+    };
+
+    if (!widen.empty()) {
+      // too narrow a window: the same solve with the window sized for twice
+      // as many eigenvalues, as one batch of its own (same block size)
+      polfed_opts ow = og;
+      ow.window_factor *= 2.0;
+      rerun(widen, first_w, ow, false, add_attempt);
+    }
+    if (!redo.empty()) {
+      // the FP64 re-solves of this group as one batch of their own (same
+      // block size), each result as a single FP64 re-solve would report it
+      polfed_opts o64 = og;
+      o64.precision = 0;
+      rerun(redo, first, o64, true, merge_resolve_info);
+    }
+
     if (std::getenv("POLFED_VERBOSE"))
       fprintf(stderr,
               "[polfed] batch group L=%d s=%d: %d members, Lanczos %.2f s (filter kernels "

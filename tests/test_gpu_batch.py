@@ -107,3 +107,37 @@ def test_batch_rejects_empty_and_oversized(ctx, pf):
     models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in (big, small)]
     with pytest.raises(pf.PolfedError):
         ctx.solve_batch(models, 21, block_size=4)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_narrow_window_is_widened(ctx, pf, precision):
+    """A realisation of the 512-member batch (L = 14, W = 5) whose Gaussian-DOS
+    window holds only 18 eigenvalues above p for N_ev = 20: both the batched
+    and the single solve repeat it with the window sized for twice as many
+    eigenvalues (info nev_window 60 instead of 30) and return the 20
+    eigenvalues nearest the target, while the members around it keep their
+    window."""
+    narrow = workloads.chain(14, 5.0, 1207)
+    others = [workloads.chain(14, 2.0, 1003), workloads.chain(14, 3.0, 1006)]
+    chains = [others[0], narrow, others[1]]
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in chains]
+    nev = 20
+    res = ctx.solve_batch(models, nev, vectors=True, block_size=8, precision=precision)
+    assert all(st == pf.OK for st in res["status"]), res["status"]
+    assert [i["nev_window"] for i in res["info"]] == [30, 60, 30]
+    for i, c in enumerate(chains):
+        H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+        w = dense.full_spectrum(H)
+        normH = max(abs(w[0]), abs(w[-1]))
+        Ed = w[dense.nearest_from_spectrum(w, res["info"][i]["sigma_energy"], nev)]
+        assert np.abs(res["E"][i] - Ed).max() <= 1e-10 * normH, i
+        V = res["V"][i]
+        assert V.shape == (H.shape[0], nev)
+        r = np.linalg.norm(H @ V - V * res["E"][i], axis=0)
+        assert r.max() <= 1e-8 * normH, (i, r.max())
+    single = ctx.solve(models[1], nev, block_size=8, precision=precision)
+    assert single["status"] == pf.OK and single["info"]["nev_window"] == 60
+    H = chain.hamiltonian_csr(narrow.L, narrow.J1, narrow.J2, narrow.Delta, narrow.h)
+    w = dense.full_spectrum(H)
+    normH = max(abs(w[0]), abs(w[-1]))
+    assert np.abs(single["E"] - res["E"][1]).max() <= 1e-10 * normH

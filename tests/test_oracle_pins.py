@@ -305,6 +305,33 @@ def test_solve_auto_K_vs_dense(L, J2, Delta, W, nev, s):
     assert res["resid"].max() <= 1e-8 * normH
 
 
+def test_solve_widens_a_window_the_dos_made_too_narrow():
+    """A short, strongly disordered chain (L = 14, W = 5, a realisation of the
+    512-member batch) whose Gaussian-DOS order leaves only 18 eigenvalues
+    with P >= p for N_ev = 20: the solve repeats with the window sized for
+    twice as many eigenvalues and then returns exactly the 20 eigenvalues
+    nearest the target; a chain whose window is wide enough keeps it."""
+    c = workloads.chain(14, 5.0, 1207)
+    H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+    w = dense.full_spectrum(H)
+    normH = max(abs(w[0]), abs(w[-1]))
+    # the window of the first attempt, counted on the exact spectrum
+    E0w, E1w = lanczos.widened_bounds(w[0], w[-1], 1e-3)
+    a, b = chebyshev.rescale_coeffs(E0w, E1w)
+    sig_t = a * (w[0] + 0.5 * (w[-1] - w[0])) + b
+    K1 = chebyshev.choose_K(lanczos.window_count(20), sig_t, 0.17, H.shape[0],
+                            float(H.diagonal().sum()) / H.shape[0],
+                            chebyshev.dos_gamma(c.L, c.J1, c.J2, c.Delta, c.h), E0w, E1w)
+    assert int((chebyshev.P_of_x(a * w + b, sig_t, K1) >= 0.17).sum()) < 20
+    res = lanczos.solve(c.L, c.J1, c.J2, c.Delta, c.h, 20, 8)
+    assert res["window_factor"] == 3.0 and res["K"] < K1
+    Ed = w[dense.nearest_from_spectrum(w, res["sigma_H"], 20)]
+    assert np.abs(res["E"] - Ed).max() <= 1e-10 * normH
+    assert res["resid"].max() <= 1e-8 * normH
+    ok = workloads.chain(14, 2.0, 1003)
+    assert lanczos.solve(ok.L, ok.J1, ok.J2, ok.Delta, ok.h, 20, 8)["window_factor"] == 1.5
+
+
 def test_lanczos_invariants():
     """Q^T Q = I, T symmetric, theta <= 1, converged theta = P(lambda~)."""
     L, nev, s = 12, 12, 4
