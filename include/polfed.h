@@ -74,7 +74,9 @@ typedef struct {
   int precision;          /* 0: FP64 filter; 1: FP32 filter, FP64 Lanczos,
                              Rayleigh-Ritz and residuals + FP64 refinement  */
   double window_factor;   /* filter window sized for ceil(f N_ev)
-                             eigenvalues; 0 -> 1.5                          */
+                             eigenvalues; 0 -> 1.5.  With K = 0 it is
+                             doubled (up to 12) while a run ends with fewer
+                             than N_ev Ritz values at theta >= p           */
   int max_cols;           /* Lanczos columns; 0 -> 8 N_win + 8 s           */
   double tol;             /* residual target relative to ||H||; 0 -> 1e-10 */
   double eta;             /* bounds margin, fraction of E1-E0; 0 -> 1e-3   */
@@ -256,8 +258,15 @@ int polfed_filter_stats(polfed_ctx *ctx, double *gpu_s, double *launches, double
  * [dim x nev] column-major (eigenvector i contiguous at evecs + i*dim),
  * each of unit norm with its largest-|.| entry positive (lowest index on
  * ties); resid[nev] = ||H v - E v||_2.  info nullable.  opts NULL means
- * defaults.  Returns POLFED_NOT_CONVERGED (with the best nev pairs) when
- * the Lanczos column cap is reached first.  Blocks until done. */
+ * defaults.  With an automatic order (K = 0), a run whose filter window
+ * turns out to hold fewer than nev Ritz values at theta >= p (the Gaussian
+ * density of states overestimated the density at the target) is repeated
+ * with the window doubled (info->nev_window reports the final one).  In FP32
+ * mode a result whose largest residual misses 1e-8 ||H|| after the
+ * refinement is recomputed with the FP64 filter (info->refine_passes = -1).
+ * Returns POLFED_NOT_CONVERGED (with the best nev pairs) when the Lanczos
+ * column cap is reached first, or the window is still too narrow at 12 N_ev.
+ * Blocks until done. */
 int polfed_solve(polfed_ctx *ctx, const polfed_model *model,
                  const polfed_opts *opts, int nev, double *evals,
                  double *evecs, double *resid, polfed_info *info);
@@ -268,7 +277,9 @@ int polfed_solve(polfed_ctx *ctx, const polfed_model *model,
  * of the per-realisation [dim_r x nev] column-major blocks; infos (nullable)
  * [R]; status[R] per realisation.  Returns the worst status.  R >= 1 and
  * 1 <= nev <= dim_r for every model, checked before any work (else
- * POLFED_EINVAL with the outputs untouched). */
+ * POLFED_EINVAL with the outputs untouched).  Window doubling and FP64
+ * re-solves as in polfed_solve, each run for the members concerned as a
+ * batch of its own. */
 int polfed_solve_batch(polfed_ctx *ctx, int R, const polfed_model *models,
                        const polfed_opts *opts, int nev, double *evals,
                        double *evecs, double *resid, polfed_info *infos,
