@@ -97,6 +97,26 @@ def test_batched_workload_members_fp32(ctx, pf):
         assert r.max() <= 1e-8 * normH, (i, r.max())
 
 
+def test_batched_workload_l14_sample_vs_dense(ctx, pf):
+    """A wider sample of the 512-realisation batch: 24 of its L = 14 members
+    (every fields strength W = 1..5), solved as one FP32 batch with the tuned
+    block size, each against the dense spectrum: the 20 eigenvalues nearest
+    the target, none skipped, residuals under the bar."""
+    wl = workloads.c4()
+    chains = [c for c in wl.chains if c.L == 14][::7][:24]
+    assert sorted({c.W for c in chains}) == [1.0, 2.0, 3.0, 4.0, 5.0]
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in chains]
+    res = ctx.solve_batch(models, wl.nev, vectors=False, block_size=8, precision=1)
+    assert all(st == pf.OK for st in res["status"]), res["status"]
+    for i, c in enumerate(chains):
+        H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+        w = dense.full_spectrum(H)
+        normH = max(abs(w[0]), abs(w[-1]))
+        Ed = w[dense.nearest_from_spectrum(w, res["info"][i]["sigma_energy"], wl.nev)]
+        assert np.abs(res["E"][i] - Ed).max() <= 1e-10 * normH, (i, c.seed)
+        assert res["resid"][i].max() <= 1e-8 * normH, (i, c.seed)
+
+
 def test_batch_rejects_empty_and_oversized(ctx, pf):
     """An empty batch and an N_ev above a member's dimension are argument
     errors (nothing is computed)."""
