@@ -265,7 +265,8 @@ int polfed_filter_stats(polfed_ctx *ctx, double *gpu_s, double *launches, double
  * mode a result whose largest residual misses 1e-8 ||H|| after the
  * refinement is recomputed with the FP64 filter (info->refine_passes = -1).
  * Returns POLFED_NOT_CONVERGED (with the best nev pairs) when the Lanczos
- * column cap is reached first, or the window is still too narrow at 12 N_ev.
+ * column cap is reached first, when the window is still too narrow at
+ * 12 N_ev, or when a returned residual exceeds max(tol, 1e-8) ||H||.
  * Blocks until done. */
 int polfed_solve(polfed_ctx *ctx, const polfed_model *model,
                  const polfed_opts *opts, int nev, double *evals,

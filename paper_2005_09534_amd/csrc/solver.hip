@@ -1120,7 +1120,13 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
   inf.filter_gpu_s = filter_gpu_s;
   inf.filter_launches = filter_launches;
   if (info) *info = inf;
-  return (converged && nout == nev) ? POLFED_OK : POLFED_NOT_CONVERGED;
+  // OK only when every returned pair meets the accuracy bar: a run can stop
+  // with N_ev converged Ritz pairs and still select an unconverged one as
+  // one of the N_ev nearest (its residual then shows it)
+  bool all_ok = nout == nev;
+  for (int i = 0; i < nout; ++i)
+    if (!(r[i] <= std::max(o.tol, kFp32ResidBar) * normH)) all_ok = false;
+  return (converged && all_ok) ? POLFED_OK : POLFED_NOT_CONVERGED;
 }
 
 
