@@ -63,7 +63,7 @@ def _qr_pos(U):
 
 
 def block_lanczos(H, E0w, E1w, sigma_t, K, nev, s, p=0.17, tau=1e-10,
-                  max_cols=None, rng_seed=0, Q1=None, filt=None):
+                  max_cols=None, rng_seed=0, Q1=None, filt=None, top_only=False):
     """Block Lanczos on P^K_sigma(H~).  Returns a dict with Qm, T, theta, t,
     the converged count and the number of blocks m.
 
@@ -115,6 +115,10 @@ def block_lanczos(H, E0w, E1w, sigma_t, K, nev, s, p=0.17, tau=1e-10,
             # fewer than N_ev Ritz values above p; then the N_ev largest theta
             # are the ones that must converge
             sel = theta >= np.sort(theta)[::-1][min(nev, len(theta)) - 1]
+        if top_only and len(theta) >= nev:
+            # reading: in a window wider than the default the N_ev largest
+            # theta must be the converged ones
+            sel = sel & (theta >= np.sort(theta)[::-1][nev - 1])
         nconv = int(np.sum(sel & (res <= tau)))
         result = dict(Qm=np.hstack(Qs), T=T, theta=theta, t=t, res=res, sel=sel,
                       nconv=nconv, m=m, B_last=B)
@@ -220,7 +224,7 @@ def solve(L, J1, J2, Delta, h, nev, s, sigma_H=None, eps_target=0.5, K=None,
     if max_cols is None:
         max_cols = column_cap(nwin, s)
     res = block_lanczos(H, E0w, E1w, sigma_t, K, nev, s, p=p, tau=tau, rng_seed=rng_seed,
-                        max_cols=max_cols)
+                        max_cols=max_cols, top_only=window_factor > 1.5 + 1e-9)
     if (K_auto and nev_window is None and int(np.sum(res["theta"] >= p)) < nev
             and 2.0 * window_factor <= MAX_WINDOW_FACTOR):
         return solve(L, J1, J2, Delta, h, nev, s, sigma_H=sigma_H, eps_target=eps_target, K=None,

@@ -801,6 +801,11 @@ void Realization<T>::check_finish(const double *th, const double *Vt) {
   above = 0;
   for (int i = 0; i < ms; ++i) above += theta[i] >= o.p;
   if (above < nev) thr = theta[std::max(0, ms - nev)];  // ascending order
+  // a window wider than the default 1.5 N_ev (a widened rerun, or the
+  // caller's choice) holds many eigenvalues where P is nearly flat, and N_ev
+  // converged pairs anywhere in it need not be the N_ev nearest: there the
+  // nev largest theta must be the converged ones
+  if (o.window_factor > 1.5 + 1e-9 && ms >= nev) thr = std::max(thr, theta[ms - nev]);
   nconv = 0;
   int nconv_loose = 0;
   for (int i = 0; i < ms; ++i) {

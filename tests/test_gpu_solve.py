@@ -253,29 +253,29 @@ def test_poor_bounds_never_return_garbage(ctx, pf, steps):
     np.testing.assert_allclose(res, r["resid"], rtol=1e-6, atol=1e-12 * normH)
 
 
-def test_status_reflects_returned_residuals(ctx, pf):
-    """A window far wider than the default (6 N_ev) makes the filter flat
-    over many eigenvalues, and a run can stop with N_ev converged pairs while
-    one of the N_ev nearest is not among them (seen on this L = 16, W = 4
-    realisation).  Whatever is returned, the status is OK only if every
-    returned residual meets max(tol, 1e-8) ||H||, and the returned residuals
-    are those of the returned vectors; the default window gets the answer."""
+def test_wide_window_returns_the_nearest(ctx, pf):
+    """A window far wider than the default (6 N_ev) makes the filter flat over
+    many eigenvalues; with the paper's count (any N_ev converged pairs above
+    p) this L = 16, W = 4 realisation stopped with an unconverged pair among
+    the N_ev nearest (residual 4e-3, returned with status OK).  For wider
+    windows the N_ev largest theta must now be the converged ones, and the
+    status is OK only when every returned residual meets max(tol, 1e-8)
+    ||H||: the wide and the default window give the same answer, which the
+    FP32-filter path confirms (and which was checked once against the full
+    spectrum: exact to 3e-16 ||H||)."""
     c = workloads.chain(16, 4.0, 1235)
     m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
     H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+    out = {}
     for wf in (6.0, 0.0):
         r = ctx.solve(m, 20, block_size=4, precision=0, window_factor=wf, vectors=True)
         normH = r["info"]["normH"]
         res = np.linalg.norm(H @ r["V"] - r["V"] * r["E"], axis=0)
         np.testing.assert_allclose(res, r["resid"], rtol=1e-6, atol=1e-12 * normH)
-        if r["status"] == pf.OK:
-            assert r["resid"].max() <= 1e-8 * normH, wf
-        else:
-            assert r["status"] == pf.NOT_CONVERGED and r["resid"].max() > 1e-8 * normH
-        if wf == 0.0:
-            # (checked once against the full spectrum: exact to 3e-16 ||H||;
-            # here against the independent FP32-filter path)
-            assert r["status"] == pf.OK
-            r32 = ctx.solve(m, 20, block_size=4, precision=1, vectors=False)
-            assert r32["status"] == pf.OK
-            assert np.abs(r["E"] - r32["E"]).max() <= 1e-10 * normH
+        assert r["status"] == pf.OK, wf
+        assert r["resid"].max() <= 1e-8 * normH, wf
+        out[wf] = r["E"]
+    assert np.abs(out[6.0] - out[0.0]).max() <= 1e-10 * normH
+    r32 = ctx.solve(m, 20, block_size=4, precision=1, vectors=False)
+    assert r32["status"] == pf.OK
+    assert np.abs(out[0.0] - r32["E"]).max() <= 1e-10 * normH
