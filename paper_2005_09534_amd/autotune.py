@@ -156,12 +156,36 @@ def tune_block(ctx, chains, nev, precision, widths=(4, 8, 16, 32), cache=None, s
                 return [r["status"]]
             return ctx.solve_batch(models, nev, block_size=s, precision=precision,
                                    vectors=False)["status"]
+
+        def timed():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = run()
+            torch.cuda.synchronize()
+            return st, (time.perf_counter() - t0) / len(models)
         run()  # warm (graph capture, buffers)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = run()
-        torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / len(models)
+        st, t = timed()
+        if len(models) > 1:
+            # the batched kernel walks many realisations per launch, where
+            # fewer persistent groups per CU can win (at L = 18, s = 4, FP32:
+            # 4 groups 7% faster than the single chain's 8): re-time the
+            # groups-per-CU choice on the sample batch, keep a change only
+            # when it gains more than 3%
+            base = tuple(ctx.get_step_shape(L, s, precision))
+            best_sh, best_st, best_t = base, st, t
+            for wpc in (2, 4, 8, 16):
+                sh = (base[0], base[1], wpc) + base[3:]
+                if wpc == base[2] or (base[0] == 1024 and wpc > 2):
+                    continue
+                ctx.set_step_shape(L, s, precision, *sh)
+                run()
+                st_w, t_w = timed()
+                if all(x == pf.OK for x in st_w) and t_w < best_t * 0.97:
+                    best_sh, best_st, best_t = sh, st_w, t_w
+            ctx.set_step_shape(L, s, precision, *best_sh)
+            if shape_cache is not None and best_sh != base:
+                shape_cache[_key("shape", L, chains[0].J2, precision, s)] = list(best_sh) + [0.0]
+            st, t = best_st, best_t
         if all(x == pf.OK for x in st):
             times[s] = t
             if best is None or t < best[1]:
