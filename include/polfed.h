@@ -202,25 +202,31 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *model, int steps,
 
 /* Launch shape of the fused Chebyshev-step kernel for chains of length L,
  * block width nvec (power of two, 1..64) and precision (0: FP64, 1: FP32):
- * threads per workgroup (256 or 1024), 16-byte loads per lane per gathered
+ * threads per workgroup (256, 512 or 1024), 16-byte loads per lane per gathered
  * row (lpl: 1, 2 or 4), persistent workgroups per compute unit (1..32),
- * whether the rank tables are staged in LDS (ignored for L > 26), whether
+ * whether the rank tables are staged in LDS (ignored for L > 28), whether
  * the streamed operands are loaded before the neighbour gathers
  * (early_loads != 0), and how neighbour ranks are found (rank_incremental
  * = 0: the two rank tables for every bond; != 0: from the row's own rank
  * by a binomial step for bonds that do not wrap round the chain, the
- * tables for the rest; the batched solve always uses the tables).  Results
- * are identical for every shape.  Entries live in the context; without one
- * the library's built-in default is used.  The autotuner
+ * tables for the rest; the batched solve always uses the tables), and
+ * into how many column slices the block is split across the eight XCDs
+ * (xcd_slices = 1, 2, 4 or 8; the workgroups of XCD x work on slice
+ * x % xcd_slices over 8 / xcd_slices of the rows, so that each XCD's L2
+ * holds more rows of a narrower slice; the Clenshaw filter then keeps its
+ * recurrence blocks slice-major; a width that does not split runs
+ * unsliced; single H applications and the forward form are never sliced).
+ * Results are identical for every shape.  Entries live in the context;
+ * without one the library's built-in default is used.  The autotuner
  * (paper_2005_09534_amd/autotune.py) searches this space. */
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads,
                           int lpl, int wg_per_cu, int lds_tables, int early_loads,
-                          int rank_incremental);
+                          int rank_incremental, int xcd_slices);
 /* The step shape in force for (L, nvec, precision): the context's entry,
  * else the built-in default.  Outputs as in polfed_set_step_shape. */
 int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads,
                           int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads,
-                          int *rank_incremental);
+                          int *rank_incremental, int *xcd_slices);
 /* Block size used when opts->block_size is 0 for chains of length L at the
  * given precision and N_ev (the autotuner's choice); without an entry a
  * built-in rule is used (about N_ev/4, capped at 16 in FP64 and 32 in FP32,
@@ -250,6 +256,16 @@ int polfed_set_filter_form(polfed_ctx *ctx, int form);
  * pointer may be NULL.  reset != 0 zeroes the counters after reading. */
 int polfed_filter_stats(polfed_ctx *ctx, double *gpu_s, double *launches, double *bytes,
                         int reset);
+
+/* Attainable device-memory bandwidth, for setting the step kernel's
+ * achieved rate beside it: copies `bytes` bytes (a positive multiple of 16;
+ * src and dst device pointers, 16-byte aligned, not overlapping) with a
+ * plain kernel of 16-byte non-temporal loads and stores, once to warm up and
+ * then `reps` times, timed with HIP events on the context's stream.  Writes
+ * *gbs = (read + written bytes) / seconds / 1e9.  Blocks until done.  The
+ * copy should be much larger than the 256 MB Infinity Cache. */
+int polfed_stream_copy(polfed_ctx *ctx, const void *src, void *dst, long long bytes, int reps,
+                       double *gbs);
 
 /* ---- the solve --------------------------------------------------------- */
 

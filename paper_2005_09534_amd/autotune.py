@@ -5,7 +5,8 @@ Two choices are tuned, both through the C ABI of libpolfed:
 * the launch shape of the fused Chebyshev-step kernel (threads per group,
   16-byte loads per lane, persistent groups per CU, rank tables in LDS,
   streamed loads before or after the neighbour gathers, neighbour ranks from
-  the tables or incrementally) for a (chain length L, block width,
+  the tables or incrementally, column slices across the XCDs) for a (chain
+  length L, block width,
   precision): each candidate applies the filter for a few dozen steps to a
   random block of the chain and is timed with the library's HIP-event
   counters; the fastest shape per HBM-second wins
@@ -29,10 +30,14 @@ import os
 import time
 
 # (threads, 16-byte loads per lane, groups per CU, LDS rank tables, streamed
-# loads issued before the gathers, incremental neighbour ranks)
-SHAPES = [(t, lpl, wpc, lds, early, ranki) for t, lpl, wpc, lds, early, ranki in
-          itertools.product((256, 1024), (1, 2, 4), (1, 2, 4, 8, 16), (1, 0), (0, 1), (0, 1))
-          if not (t == 1024 and wpc > 2)]
+# loads issued before the gathers, incremental neighbour ranks, XCD column
+# slices)
+LAUNCH = [(t, lpl, wpc) for t, lpl, wpc in
+          itertools.product((256, 512, 1024), (1, 2, 4), (1, 2, 4, 8, 16))
+          if wpc * t <= 2048]
+SHAPES = [(t, lpl, wpc, lds, early, ranki, xcd)
+          for (t, lpl, wpc), lds, early, ranki, xcd in
+          itertools.product(LAUNCH, (1, 0), (0, 1), (0, 1), (1, 2, 4, 8))]
 
 
 def cache_path():
@@ -59,12 +64,23 @@ def _key(kind, L, J2, precision, x):
     return f"{kind}:{L}:{int(J2 != 0.0)}:{precision}:{x}"
 
 
-def tune_shape(ctx, chain, width, precision, steps=None, shapes=SHAPES, cache=None, margin=0.03):
+def staged_candidates(best, width):
+    """Second stage of the default search: the launch shapes (threads, loads
+    per lane, groups per CU) with every column-slice count that splits the
+    width, the other fields as in `best`."""
+    return [(t, lpl, wpc) + tuple(best[3:6]) + (xcd,)
+            for (t, lpl, wpc) in LAUNCH for xcd in (2, 4, 8) if xcd <= width]
+
+
+def tune_shape(ctx, chain, width, precision, steps=None, shapes=None, cache=None, margin=0.03):
     """Fastest step-kernel shape for the chain's L at this width/precision.
 
-    The shape in force (the library default, or an earlier choice) is kept
-    unless another is faster by more than `margin`, so that near-ties do not
-    flip the choice from run to run.  Leaves the choice set on ctx; returns
+    With `shapes` given, every candidate in it is timed.  By default the
+    search has two stages: every unsliced shape, then the launch shapes with
+    2, 4 and 8 column slices around the best of the first stage.  The shape
+    in force (the library default, or an earlier choice) is kept unless
+    another is faster by more than `margin`, so that near-ties do not flip
+    the choice from run to run.  Leaves the choice set on ctx; returns
     (shape, GB/s)."""
     import torch
     from . import polfed as pf
@@ -87,12 +103,24 @@ def tune_shape(ctx, chain, width, precision, steps=None, shapes=SHAPES, cache=No
 
     current = tuple(ctx.get_step_shape(chain.L, width, precision))
     best = (current, rate(current))
-    for sh in shapes:
-        if tuple(sh) == current:
-            continue
-        gbs = rate(sh)
-        if gbs > best[1] * (1.0 + margin if best[0] == current else 1.0):
-            best = (tuple(sh), gbs)
+    seen = {current}
+
+    def search(cands):
+        nonlocal best
+        for sh in cands:
+            sh = tuple(sh)
+            if sh in seen:
+                continue
+            seen.add(sh)
+            gbs = rate(sh)
+            if gbs > best[1] * (1.0 + margin if best[0] == current else 1.0):
+                best = (sh, gbs)
+
+    if shapes is not None:
+        search(shapes)
+    else:
+        search([sh for sh in SHAPES if sh[6] == 1])
+        search(staged_candidates(best[0], width))
     ctx.set_step_shape(chain.L, width, precision, *best[0])
     if cache is not None:
         cache[_key("shape", chain.L, chain.J2, precision, width)] = list(best[0]) + [best[1]]
@@ -175,7 +203,7 @@ def tune_block(ctx, chains, nev, precision, widths=(4, 8, 16, 32), cache=None, s
             best_sh, best_st, best_t = base, st, t
             for wpc in (2, 4, 8, 16):
                 sh = (base[0], base[1], wpc) + base[3:]
-                if wpc == base[2] or (base[0] == 1024 and wpc > 2):
+                if wpc == base[2] or wpc * base[0] > 2048:
                     continue
                 ctx.set_step_shape(L, s, precision, *sh)
                 run()
@@ -211,9 +239,9 @@ def apply_cache(ctx, cache):
         kind, L, _j2, prec, x = k.split(":")
         if kind == "shape":
             # entries are the shape followed by its GB/s; older ones lack the
-            # rank-mode field (tables then)
+            # rank-mode field (tables then) and the column slices (none)
             sh = [int(t) for t in v[:-1]]
-            sh = (sh + [0])[:6] if len(sh) < 6 else sh[:6]
+            sh = (sh + [0, 1][len(sh) - 5:])[:7]
             ctx.set_step_shape(int(L), int(x), int(prec), *sh)
         elif kind == "block":
             ctx.set_block_size(int(L), int(prec), int(x), int(v[0]))

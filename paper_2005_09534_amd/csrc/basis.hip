@@ -8,7 +8,8 @@
 // bit.  Ranking uses two tables split at bit `half` = L/2: the low half
 // contributes sum over its own set bits, and the high half's bits have
 // known index t = (L/2 - popcount(hi)) + u, so each half's term is a table
-// lookup and rank(s) = tabA[hi] + tabB[lo].
+// lookup and rank(s) = tabA[hi] + tabB[lo].  tabB[lo] is a rank among the
+// C(half, popcount(lo)) <= C(15, 7) low patterns and fits 16 bits.
 #include "internal.h"
 
 namespace polfed {
@@ -47,14 +48,14 @@ __global__ void k_unrank(uint32_t *states, long long n, int L) {
 // tabB[lo] = sum over set bits q (ascending, index t = 1, 2, ...) of C(q, t)
 // tabA[hi] = sum over set bits q of hi (index t continuing after the
 //            L/2 - popcount(hi) bits below) of C(half + q, t)
-__global__ void k_rank_tables(int32_t *tabA, int32_t *tabB, int L, int half) {
+__global__ void k_rank_tables(int32_t *tabA, uint16_t *tabB, int L, int half) {
   int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= (1 << half)) return;
   int t = 0;
   uint32_t sb = 0;
   for (int q = 0; q < half; ++q)
     if ((x >> q) & 1) sb += c_binom[q][++t];
-  tabB[x] = (int32_t)sb;
+  tabB[x] = (uint16_t)sb;
   int below = L / 2 - __popc((uint32_t)x);
   uint32_t sa = 0;
   if (below >= 0) {
@@ -66,7 +67,7 @@ __global__ void k_rank_tables(int32_t *tabA, int32_t *tabB, int L, int half) {
 }
 
 __global__ void k_rank(const uint32_t *states, int32_t *ranks, long long n, const int32_t *tabA,
-                       const int32_t *tabB, int L, int half) {
+                       const uint16_t *tabB, int L, int half) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t s = states[i];
@@ -85,12 +86,12 @@ void build_basis(hipStream_t st, Basis &b, int L) {
   b.n = polfed_dim(L);
   b.states.ensure(sizeof(uint32_t) * b.n);
   b.tabA.ensure(sizeof(int32_t) << b.half);
-  b.tabB.ensure(sizeof(int32_t) << b.half);
+  b.tabB.ensure(sizeof(uint16_t) << b.half);
   int th = 256;
   k_unrank<<<(unsigned)((b.n + th - 1) / th), th, 0, st>>>(b.states.as<uint32_t>(), b.n, L);
   check_launch("k_unrank");
   k_rank_tables<<<(unsigned)(((1 << b.half) + th - 1) / th), th, 0, st>>>(
-      b.tabA.as<int32_t>(), b.tabB.as<int32_t>(), L, b.half);
+      b.tabA.as<int32_t>(), b.tabB.as<uint16_t>(), L, b.half);
   check_launch("k_rank_tables");
   b.binom.ensure(sizeof(int32_t) * 32 * 32);
   k_binom_table<<<4, 256, 0, st>>>(b.binom.as<int32_t>());
@@ -102,7 +103,7 @@ void launch_rank(hipStream_t st, const Basis &b, long long n, const uint32_t *st
   if (n <= 0) return;
   int th = 256;
   k_rank<<<(unsigned)((n + th - 1) / th), th, 0, st>>>(states, ranks, n, b.tabA.as<int32_t>(),
-                                                      b.tabB.as<int32_t>(), b.L, b.half);
+                                                      b.tabB.as<uint16_t>(), b.L, b.half);
   check_launch("k_rank");
 }
 

@@ -335,14 +335,18 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *m, int steps, unsigned lo
 }
 
 int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads, int lpl,
-                          int wg_per_cu, int lds_tables, int early_loads, int rank_incremental) {
+                          int wg_per_cu, int lds_tables, int early_loads, int rank_incremental,
+                          int xcd_slices) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
     PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
     PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
-    PF_REQUIRE(threads == 256 || threads == 1024, "threads must be 256 or 1024");
+    PF_REQUIRE(threads == 256 || threads == 512 || threads == 1024,
+               "threads must be 256, 512 or 1024");
     PF_REQUIRE(lpl == 1 || lpl == 2 || lpl == 4, "lpl must be 1, 2 or 4");
     PF_REQUIRE(wg_per_cu >= 1 && wg_per_cu <= 32, "wg_per_cu must be in [1, 32]");
+    PF_REQUIRE(xcd_slices == 1 || xcd_slices == 2 || xcd_slices == 4 || xcd_slices == 8,
+               "xcd_slices must be 1, 2, 4 or 8");
     StepShape sh;
     sh.threads = threads;
     sh.lpl = lpl;
@@ -350,6 +354,7 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
     sh.lds_tables = lds_tables ? 1 : 0;
     sh.early_loads = early_loads ? 1 : 0;
     sh.rank_incr = rank_incremental ? 1 : 0;
+    sh.xcd_slices = xcd_slices;
     ctx->shapes[std::make_tuple(L, nvec, precision ? 4 : 8)] = sh;
     return POLFED_OK;
   });
@@ -357,12 +362,13 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
 
 int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads, int *lpl,
                           int *wg_per_cu, int *lds_tables, int *early_loads,
-                          int *rank_incremental) {
+                          int *rank_incremental, int *xcd_slices) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
     PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
     PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
-    PF_REQUIRE(threads && lpl && wg_per_cu && lds_tables && early_loads && rank_incremental,
+    PF_REQUIRE(threads && lpl && wg_per_cu && lds_tables && early_loads && rank_incremental &&
+                   xcd_slices,
                "NULL output");
     auto it = ctx->shapes.find(std::make_tuple(L, nvec, precision ? 4 : 8));
     const StepShape sh = (it != ctx->shapes.end()) ? it->second : default_shape(L, nvec, precision != 0);
@@ -372,6 +378,7 @@ int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *
     *lds_tables = sh.lds_tables;
     *early_loads = sh.early_loads;
     *rank_incremental = sh.rank_incr;
+    *xcd_slices = sh.xcd_slices;
     return POLFED_OK;
   });
 }
@@ -414,6 +421,19 @@ int polfed_filter_stats(polfed_ctx *ctx, double *gpu_s, double *launches, double
       ctx->filter_launches = 0.0;
       ctx->filter_bytes = 0.0;
     }
+    return POLFED_OK;
+  });
+}
+
+int polfed_stream_copy(polfed_ctx *ctx, const void *src, void *dst, long long bytes, int reps,
+                       double *gbs) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(src && dst && gbs, "NULL argument");
+    PF_REQUIRE(bytes >= 16 && bytes % 16 == 0, "bytes must be a positive multiple of 16");
+    PF_REQUIRE(reps >= 1, "reps must be >= 1");
+    PF_REQUIRE((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 == 0,
+               "src and dst must be 16-byte aligned");
+    *gbs = stream_copy_gbs(ctx->stream, src, dst, bytes, reps, ctx->num_cu);
     return POLFED_OK;
   });
 }

@@ -1,540 +1,41 @@
-// Matrix-free application of H~ fused with one three-term Chebyshev step.
-//
-//   out[r,:] = alpha X[r,:] + dscale dt[r] V[r,:] + sum_bonds w_l V[r',:]
-//              + gamma W[r,:]
-//
-// H of eq. (XXZ) has, in row r (state s), the diagonal d_r and an entry J_l/2
-// at the row r' of s with an antiparallel pair (i, i+l mod L) swapped
-// (Supplement, "Technical details": the off-diagonal values are all equal,
-// so nothing but the pattern is needed -- and here not even the pattern is
-// stored: it is regenerated from s).  H is symmetric, so y = Hx is a pure
-// row gather: no atomics.
-//
-// One Clenshaw step b_k = c_k X + 2 H~ b_{k+1} - b_{k+2} is this kernel with
-// alpha = c_k, V = b_{k+1}, dscale = 2 (dt = a d + b), w_l = a J_l, W =
-// b_{k+2}, gamma = -1; the last step Y = (c_0 X + H~ b_1 - b_2)/D uses
-// alpha = c_0/D, dscale = 1/D, w_l = a J_l/(2D), gamma = -1/D.
-//
-// Layout: blocks are row-major (the s values of a row contiguous), so one
-// gathered neighbour is one contiguous s * sizeof(T) segment.  A row is
-// owned by G lanes, each moving VEC = 16/sizeof(T) * LPL elements with 16-byte
-// vector loads; 64/G rows share a wavefront.  Workgroups are persistent;
-// each XCD sweeps one contiguous eighth of the rows with all its groups in
-// step (see the tile schedule below), which keeps the gathers of a row's
-// own bit segment inside that XCD's L2.  The rank tables are staged in LDS
-// once per workgroup.
-//
-// Ranks of neighbours come from the two tables, or (RANKI) incrementally
-// from the row's own rank: in the colex rank sum_t C(p_t, t), moving the
-// particle with q particles below it from bit i to bit i+1 adds C(i, q)
-// (Pascal's rule on its one term); a hop from i to i+2 adds C(i, q) +
-// C(i+1, q + n_{i+1}) (two such moves, the second one over or past the
-// particle at i+1); the reverse moves subtract the same.  Bonds that wrap
-// round the chain renumber every particle and take the tables.
-//
-// The forward three-term form t_{k+1} = 2 H~ t_k - t_{k-1} (the sum of
-// c_k T_k(H~) X accumulated term by term) is this kernel with W = t_{k-1}
-// and the fused accumulation acc = cin src + cacc out.
-#include <algorithm>
-#include <type_traits>
-
-#include "internal.h"
+// FP64 instantiations of the fused Chebyshev step (hv_kernels.h), and the
+// small layout kernels of the filter: slice packing and precision casts.
+#include "hv_kernels.h"
 
 namespace polfed {
 
-template <class T, int N>
-struct alignas(sizeof(T) * N) VecT {
-  T v[N];
-};
-
-template <class T, int S, int LPL>
-struct StepCfg {
-  static constexpr int kV16 = 16 / (int)sizeof(T);             // elements per 16 B
-  static constexpr int VEC = (S >= kV16 * LPL) ? kV16 * LPL : (S >= kV16 ? kV16 : S);
-  static constexpr int G = S / VEC;                               // lanes per row
-  static_assert(G >= 1 && G <= 64, "row must fit a wavefront");
-  static constexpr int RPW = 64 / G;                              // rows per wave
-  static constexpr int NLD = (VEC * (int)sizeof(T) >= 16) ? VEC * (int)sizeof(T) / 16 : 1;
-  static constexpr int LDV = (VEC * (int)sizeof(T) >= 16) ? 16 / (int)sizeof(T) : VEC;
-};
-
-template <class T, int VEC, int LDV>
-__device__ __forceinline__ void load_row(const T *__restrict__ p, T (&v)[VEC]) {
-#pragma unroll
-  for (int k = 0; k < VEC; k += LDV) {
-    VecT<T, LDV> t = *reinterpret_cast<const VecT<T, LDV> *>(p + k);
-#pragma unroll
-    for (int e = 0; e < LDV; ++e) v[k + e] = t.v[e];
-  }
-}
-
-// Streaming rows (X, W in, the output out) are touched once per step:
-// non-temporal accesses keep them from displacing the gathered block in L2.
-template <class T, int VEC, int LDV>
-__device__ __forceinline__ void load_row_nt(const T *__restrict__ p, T (&v)[VEC]) {
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) v[k] = __builtin_nontemporal_load(p + k);
-}
-
-template <class T, int VEC, int LDV>
-__device__ __forceinline__ void store_row_nt(T *__restrict__ p, const T (&v)[VEC]) {
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) __builtin_nontemporal_store(v[k], p + k);
-}
-
-template <class T, int VEC, int LDV>
-__device__ __forceinline__ void store_row(T *__restrict__ p, const T (&v)[VEC]) {
-#pragma unroll
-  for (int k = 0; k < VEC; k += LDV) {
-    VecT<T, LDV> t;
-#pragma unroll
-    for (int e = 0; e < LDV; ++e) t.v[e] = v[k + e];
-    *reinterpret_cast<VecT<T, LDV> *>(p + k) = t;
-  }
-}
-
-// Neighbours gathered per batch: enough loads in flight per lane for memory-
-// level parallelism while the batch stays within ~32 registers of data.
-template <int VEC>
-struct Chunk {
-  static constexpr int value = (32 / VEC) > 8 ? 8 : ((32 / VEC) < 2 ? 2 : 32 / VEC);
-};
-
-// One row of the fused step: out[r,:] for the lanes (col .. col+VEC) this
-// thread owns.  tA / tB are the rank tables (LDS or global).
-template <class T, int S, int LPL, bool EARLY, bool RANKI>
-__device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int col,
-                                         const int32_t *__restrict__ tA,
-                                         const int32_t *__restrict__ tB,
-                                         const int32_t *__restrict__ tC) {
-  using C = StepCfg<T, S, LPL>;
-  constexpr int VEC = C::VEC, LDV = C::LDV;
-  constexpr int kChunk = Chunk<VEC>::value;
-  const int L = a.L;
-  const uint32_t fullmask = a.fullmask;
-  const uint32_t lomask = a.lomask;
-  const int half = a.half;
-
-  T acc[VEC];
-#pragma unroll
-  for (int e = 0; e < VEC; ++e) acc[e] = T(0);
-  // EARLY: the streamed operands do not depend on the gathers; issuing their
-  // loads first overlaps their latency with the neighbour rounds (a gain
-  // where a step is one round of latency, small chains) at the cost of
-  // registers held across the gathers.  Either way they are added last, in
-  // the same order, so the result does not depend on EARLY.
-  T x[VEC], w[VEC];
-  if (EARLY) {
-    if (a.X != nullptr) load_row_nt<T, VEC, LDV>(a.X + (size_t)r * a.ldx + col, x);
-    if (a.W != nullptr) load_row_nt<T, VEC, LDV>(a.W + (size_t)r * a.ldw + col, w);
-  }
-
-  if (a.V != nullptr) {
-    const uint32_t s = a.states[r];
-    T self[VEC];
-    load_row<T, VEC, LDV>(a.V + (size_t)r * a.ldv + col, self);
-    const T dd = a.dscale * a.dt[r];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] = dd * self[e];
-
-    // antiparallel bonds: bit i of s ^ rot_l(s) marks the pair (i, i+l)
-    const uint32_t rot1 = ((s >> 1) | (s << (L - 1))) & fullmask;
-    unsigned long long mm = (unsigned long long)(s ^ rot1);
-    if (a.has_j2) {
-      const uint32_t rot2 = ((s >> 2) | (s << (L - 2))) & fullmask;
-      mm |= (unsigned long long)(s ^ rot2) << 32;
-    }
-    // Neighbours go in chunks of kChunk: the rank-table lookups of chunk c+1
-    // are issued right after the gathers of chunk c, so each chunk costs one
-    // round of memory latency (lookups and gathers overlap) rather than two.
-    // Bits are taken in the same order either way, so the sum is unchanged.
-    auto fill = [&](int32_t(&idx)[kChunk], bool(&two)[kChunk]) {
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        idx[u] = -1;
-        two[u] = false;
-        if (mm) {
-          const int bit = __ffsll((long long)mm) - 1;
-          mm &= mm - 1ull;
-          const int l = (bit >= 32) ? 2 : 1;
-          const int i = bit & 31;
-          int j = i + l;
-          if (j >= L) j -= L;
-          if (RANKI && j > i) {
-            const int q = __popc(s & ((1u << i) - 1u));
-            int d = tC[32 * i + q];
-            if (l == 2) d += tC[32 * (i + 1) + q + (int)((s >> (i + 1)) & 1u)];
-            idx[u] = ((s >> i) & 1u) ? (int32_t)r + d : (int32_t)r - d;
-          } else {
-            const uint32_t f = s ^ ((1u << i) | (1u << j));
-            idx[u] = tA[f >> half] + tB[f & lomask];
-          }
-          two[u] = (l == 2);
-        }
-      }
-    };
-    int32_t idx[kChunk];
-    bool two[kChunk];
-    fill(idx, two);
-    for (;;) {
-      T nb[kChunk][VEC];
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        if (idx[u] >= 0) load_row<T, VEC, LDV>(a.V + (size_t)idx[u] * a.ldv + col, nb[u]);
-      }
-      const bool more = (mm != 0ull);
-      int32_t idx2[kChunk];
-      bool two2[kChunk];
-      fill(idx2, two2);  // no-op lookups when nothing is left
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        if (idx[u] >= 0) {
-          const T w = two[u] ? a.w2 : a.w1;
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[e] += w * nb[u][e];
-        }
-      }
-      if (!more) break;
-#pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        idx[u] = idx2[u];
-        two[u] = two2[u];
-      }
-    }
-  }
-
-  if (a.X != nullptr) {
-    if (!EARLY) load_row_nt<T, VEC, LDV>(a.X + (size_t)r * a.ldx + col, x);
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] += a.alpha * x[e];
-  }
-  if (a.W != nullptr) {
-    if (!EARLY) load_row_nt<T, VEC, LDV>(a.W + (size_t)r * a.ldw + col, w);
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) acc[e] += a.gamma * w[e];
-  }
-  if (!a.skip_out) store_row_nt<T, VEC, LDV>(a.out + (size_t)r * a.ldo + col, acc);
-  if (a.acc != nullptr) {
-    T src[VEC];
-    load_row_nt<T, VEC, LDV>(a.src + (size_t)r * a.ldsrc + col, src);
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) src[e] = a.cin * src[e] + a.cacc * acc[e];
-    store_row_nt<T, VEC, LDV>(a.acc + (size_t)r * a.ldacc + col, src);
-  }
-}
-
-// Stage the two rank tables in LDS (when LDS_TAB) and return their bases.
-template <bool LDS_TAB, bool RANKI>
-__device__ __forceinline__ void stage_tables(const int32_t *gA, const int32_t *gB,
-                                             const int32_t *gC, int half, int32_t *s_tab,
-                                             const int32_t *&tA, const int32_t *&tB,
-                                             const int32_t *&tC) {
-  tA = gA;
-  tB = gB;
-  tC = gC;
-  if (LDS_TAB) {
-    const int tsz = 1 << half;
-    for (int i = threadIdx.x; i < tsz; i += blockDim.x) {
-      s_tab[i] = gA[i];
-      s_tab[tsz + i] = gB[i];
-    }
-    if (RANKI)
-      for (int i = threadIdx.x; i < 32 * 32; i += blockDim.x) s_tab[2 * tsz + i] = gC[i];
-    __syncthreads();
-    tA = s_tab;
-    tB = s_tab + tsz;
-    if (RANKI) tC = s_tab + 2 * tsz;
-  }
-}
-
-// Tile range of physical group b of nwg over ntiles tiles.  Physical group b
-// runs on XCD b % 8 (groups are dealt to the XCDs round-robin); XCD x owns
-// the contiguous tile range [x TX, (x+1) TX) and its W = nwg/8 groups stride
-// through it together, so the rows in flight on one XCD form one contiguous
-// window: the neighbours a row gathers from its own bit segment (and, in a
-// batch, its own realisation) are then mostly in that XCD's L2.
-__device__ __forceinline__ void xcd_tiles(long long ntiles, long long &t_begin, long long &t_end,
-                                          long long &t_step) {
-  const unsigned nwg = gridDim.x;
-  const unsigned b = blockIdx.x;
-  if ((nwg & 7u) == 0u) {
-    const long long W = nwg >> 3;
-    const long long TX = (ntiles + 7) / 8;
-    const long long x = b & 7u, slot_g = b >> 3;
-    t_begin = x * TX + slot_g;
-    t_end = (x + 1) * TX < ntiles ? (x + 1) * TX : ntiles;
-    t_step = W;
-  } else {
-    t_begin = b;
-    t_end = ntiles;
-    t_step = nwg;
-  }
-}
-
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
-__global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
-  using C = StepCfg<T, S, LPL>;
-  constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
-  extern __shared__ int32_t s_tab[];
-  const int32_t *tA, *tB, *tC;
-  stage_tables<LDS_TAB, RANKI>(a.tabA, a.tabB, a.binom, a.half, s_tab, tA, tB, tC);
-
-  const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
-  const long long ntiles = (a.n + rows_per_iter - 1) / rows_per_iter;
-  long long t_begin, t_end, t_step;
-  xcd_tiles(ntiles, t_begin, t_end, t_step);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int slot = lane / G;
-  const int col = (lane % G) * VEC;
-  for (long long t = t_begin; t < t_end; t += t_step) {
-    const long long r = t * rows_per_iter + (long long)wave * RPW + slot;
-    if (r >= a.n) continue;
-    step_row<T, S, LPL, EARLY, RANKI>(a, r, col, tA, tB, tC);
-  }
-}
-
-// Batched Clenshaw step for B realisations of one chain length L (same
-// basis, block width S): realisation i has its own diagonal, coefficients,
-// order K_i and buffers.  At global step j (0 <= j <= Kmax), realisation i
-// is at local step j_i = j - (Kmax - K_i) (idle while j_i < 0), so that all
-// end together; step Kmax is the final combination Y = (c_0 X + H~ b_1 -
-// b_2)/D.  Tiles run realisation-major, so an XCD works through whole
-// realisations.
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY>
-__global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const BatchItem<T> *items,
-                                                       int B, long long j, long long Kmax) {
-  using C = StepCfg<T, S, LPL>;
-  constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
-  extern __shared__ int32_t s_tab[];
-  const int32_t *tA, *tB, *tC;
-  stage_tables<LDS_TAB, false>(base.tabA, base.tabB, base.binom, base.half, s_tab, tA, tB, tC);
-
-  const long long n = base.n;
-  const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
-  const long long tper = (n + rows_per_iter - 1) / rows_per_iter;
-  long long t_begin, t_end, t_step;
-  xcd_tiles(tper * B, t_begin, t_end, t_step);
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int slot = lane / G;
-  const int col = (lane % G) * VEC;
-  for (long long t = t_begin; t < t_end; t += t_step) {
-    const int i = (int)(t / tper);
-    const BatchItem<T> it = items[i];
-    const long long ji = j - (Kmax - it.K);
-    if (!it.active || ji < 0) continue;
-    const long long r = (t - (long long)i * tper) * rows_per_iter + (long long)wave * RPW + slot;
-    if (r >= n) continue;
-    StepArgs<T> a = base;
-    a.dt = it.dt;
-    const size_t blk = (size_t)n * S;
-    T *bufs[3] = {it.buf, it.buf + blk, it.buf + 2 * blk};
-    a.ldv = a.ldw = a.ldo = a.ldx = S;
-    if (j < Kmax) {
-      const long long k = it.K - ji;
-      a.out = bufs[ji % 3];
-      a.V = (ji >= 1) ? bufs[(ji - 1) % 3] : nullptr;
-      a.W = (ji >= 2) ? bufs[(ji - 2) % 3] : nullptr;
-      const double ck = it.coef[k];
-      a.X = (ck != 0.0) ? it.X : nullptr;
-      a.alpha = (T)ck;
-      a.dscale = T(2);
-      a.w1 = it.w1;
-      a.w2 = it.w2;
-      a.gamma = T(-1);
-    } else {
-      a.out = it.Y;
-      a.X = it.X;
-      a.alpha = (T)(it.coef[0] * it.Dinv);
-      a.V = (it.K >= 1) ? bufs[(it.K - 1) % 3] : nullptr;
-      a.W = (it.K >= 2) ? bufs[(it.K - 2) % 3] : nullptr;
-      a.dscale = (T)it.Dinv;
-      a.w1 = (T)(0.5 * (double)it.w1 * it.Dinv);
-      a.w2 = (T)(0.5 * (double)it.w2 * it.Dinv);
-      a.gamma = (T)(-it.Dinv);
-    }
-    step_row<T, S, LPL, EARLY, false>(a, r, col, tA, tB, tC);
-  }
-}
-
-// Calls f.template operator()<LDS_TAB, MAXT, EARLY, RANKI>() for the
-// runtime choice (RANKI only where the launcher uses it).
-template <bool RANKI_USED, class F>
-static void dispatch_shape(bool lds, int threads, bool early, bool ranki, F &&f) {
-  if (threads != 256 && threads != 1024)
-    throw Error(POLFED_EINVAL, "step kernel: threads must be 256 or 1024");
-  auto with_rank = [&](auto lds_c, auto thr_c, auto early_c) {
-    constexpr bool LD = decltype(lds_c)::value;
-    constexpr int TH = decltype(thr_c)::value;
-    constexpr bool EA = decltype(early_c)::value;
-    if (RANKI_USED && ranki)
-      f.template operator()<LD, TH, EA, RANKI_USED>();
-    else
-      f.template operator()<LD, TH, EA, false>();
-  };
-  using T_ = std::true_type;
-  using F_ = std::false_type;
-  using I256 = std::integral_constant<int, 256>;
-  using I1024 = std::integral_constant<int, 1024>;
-  if (threads == 1024) {
-    if (lds)
-      early ? with_rank(T_{}, I1024{}, T_{}) : with_rank(T_{}, I1024{}, F_{});
-    else
-      early ? with_rank(F_{}, I1024{}, T_{}) : with_rank(F_{}, I1024{}, F_{});
-  } else {
-    if (lds)
-      early ? with_rank(T_{}, I256{}, T_{}) : with_rank(T_{}, I256{}, F_{});
-    else
-      early ? with_rank(F_{}, I256{}, T_{}) : with_rank(F_{}, I256{}, F_{});
-  }
-}
-
-// Launchers of the two step kernels for one (T, S, LPL), called by
-// dispatch_shape with the remaining template parameters.
-template <class T, int S, int LPL>
-struct StepLaunch {
-  hipStream_t st;
-  const StepArgs<T> &a;
-  long long nwg;
-  int threads;
-  size_t shm;
-  template <bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
-  void operator()() const {
-    // L = 26 tables (64 KB) plus the binomials exceed the default 64 KB of
-    // dynamic LDS per group
-    if (LDS_TAB && shm > 65536)
-      PF_HIP(hipFuncSetAttribute(
-          reinterpret_cast<const void *>(k_step<T, S, LPL, LDS_TAB, MAXT, EARLY, RANKI>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    k_step<T, S, LPL, LDS_TAB, MAXT, EARLY, RANKI>
-        <<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a);
-  }
-};
-
-template <class T, int S, int LPL>
-struct BatchedLaunch {
-  hipStream_t st;
-  const StepArgs<T> &a;
-  const BatchItem<T> *items;
-  int B;
-  long long j, Kmax, nwg;
-  int threads;
-  size_t shm;
-  template <bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
-  void operator()() const {
-    k_step_batched<T, S, LPL, LDS_TAB, MAXT, EARLY>
-        <<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a, items, B, j, Kmax);
-  }
-};
-
-template <class T, int S, int LPL>
-static void launch_step_s(hipStream_t st, const StepArgs<T> &a0, const StepShape &shape,
-                          int num_cu) {
-  using C = StepCfg<T, S, LPL>;
-  StepArgs<T> a = a0;
-  const int threads = shape.threads;
-  const long long rows_per_iter = (long long)(threads / 64) * C::RPW;
-  long long want = (long long)num_cu * shape.wg_per_cu;
-  long long tiles = (a.n + rows_per_iter - 1) / rows_per_iter;
-  long long nwg = std::min(want, tiles);
-  // a multiple of 8 lets the kernel apply its per-XCD schedule; extra
-  // groups find no tile and exit
-  nwg = ((nwg + 7) / 8) * 8;
-  a.rows_per_wg = rows_per_iter;
-  const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
-  const bool ranki = shape.rank_incr != 0;
-  const size_t shm =
-      lds ? sizeof(int32_t) * ((size_t)2 * ((size_t)1 << a.half) + (ranki ? 32 * 32 : 0)) : 0;
-  dispatch_shape<true>(lds, threads, shape.early_loads != 0, ranki,
-                       StepLaunch<T, S, LPL>{st, a, nwg, threads, shm});
-  check_launch("k_step");
-}
-
-template <class T, int S, int LPL>
-static void launch_batched_s(hipStream_t st, const StepArgs<T> &a, const BatchItem<T> *items,
-                             int B, long long j, long long Kmax, const StepShape &shape,
-                             int num_cu) {
-  using C = StepCfg<T, S, LPL>;
-  const int threads = shape.threads;
-  const long long rows_per_iter = (long long)(threads / 64) * C::RPW;
-  const long long tiles = ((a.n + rows_per_iter - 1) / rows_per_iter) * B;
-  long long nwg = std::min((long long)num_cu * shape.wg_per_cu, tiles);
-  nwg = ((nwg + 7) / 8) * 8;
-  const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
-  const size_t shm = lds ? (size_t)2 * sizeof(int32_t) * ((size_t)1 << a.half) : 0;
-  dispatch_shape<false>(lds, threads, shape.early_loads != 0, false,
-                        BatchedLaunch<T, S, LPL>{st, a, items, B, j, Kmax, nwg, threads, shm});
-  check_launch("k_step_batched");
-}
-
-template <class T, int S>
-static void launch_step_lpl(hipStream_t st, const StepArgs<T> &a, const StepShape &shape,
-                            int num_cu) {
-  switch (shape.lpl) {
-    case 2: launch_step_s<T, S, 2>(st, a, shape, num_cu); break;
-    case 4: launch_step_s<T, S, 4>(st, a, shape, num_cu); break;
-    default: launch_step_s<T, S, 1>(st, a, shape, num_cu); break;
-  }
-}
-
-template <class T>
-void launch_step(hipStream_t st, int S, const StepArgs<T> &a, const StepShape &shape,
-                 int num_cu) {
-  if (a.n <= 0) return;
-  switch (S) {
-    case 1: launch_step_lpl<T, 1>(st, a, shape, num_cu); break;
-    case 2: launch_step_lpl<T, 2>(st, a, shape, num_cu); break;
-    case 4: launch_step_lpl<T, 4>(st, a, shape, num_cu); break;
-    case 8: launch_step_lpl<T, 8>(st, a, shape, num_cu); break;
-    case 16: launch_step_lpl<T, 16>(st, a, shape, num_cu); break;
-    case 32: launch_step_lpl<T, 32>(st, a, shape, num_cu); break;
-    case 64: launch_step_lpl<T, 64>(st, a, shape, num_cu); break;
-    default: throw Error(POLFED_EINVAL, "block width must be a power of two in [1, 64]");
-  }
-}
-
-template <class T>
-void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const BatchItem<T> *items,
-                         int B, long long j, long long Kmax, const StepShape &shape, int num_cu) {
-  if (a.n <= 0 || B <= 0) return;
-  if (shape.threads != 256 && shape.threads != 1024)
-    throw Error(POLFED_EINVAL, "step kernel: threads must be 256 or 1024");
-#define PF_BATCH_CASE(SS)                                                              \
-  case SS:                                                                             \
-    if (shape.lpl == 2)                                                                \
-      launch_batched_s<T, SS, 2>(st, a, items, B, j, Kmax, shape, num_cu);             \
-    else if (shape.lpl == 4)                                                           \
-      launch_batched_s<T, SS, 4>(st, a, items, B, j, Kmax, shape, num_cu);             \
-    else                                                                               \
-      launch_batched_s<T, SS, 1>(st, a, items, B, j, Kmax, shape, num_cu);             \
-    break;
-  switch (S) {
-    PF_BATCH_CASE(1)
-    PF_BATCH_CASE(2)
-    PF_BATCH_CASE(4)
-    PF_BATCH_CASE(8)
-    PF_BATCH_CASE(16)
-    PF_BATCH_CASE(32)
-    PF_BATCH_CASE(64)
-    default: throw Error(POLFED_EINVAL, "block width must be a power of two in [1, 64]");
-  }
-#undef PF_BATCH_CASE
-}
-
-template void launch_step_batched<float>(hipStream_t, int, const StepArgs<float> &,
-                                         const BatchItem<float> *, int, long long, long long,
-                                         const StepShape &, int);
 template void launch_step_batched<double>(hipStream_t, int, const StepArgs<double> &,
                                           const BatchItem<double> *, int, long long, long long,
                                           const StepShape &, int);
-
-template void launch_step<float>(hipStream_t, int, const StepArgs<float> &, const StepShape &,
-                                 int);
 template void launch_step<double>(hipStream_t, int, const StepArgs<double> &,
                                   const StepShape &, int);
 
 // -------------------------------------------------------------- casts --
+
+template <class T>
+__global__ void k_pack_slices(long long n, int S, int sw, const T *X, long long ldx, T *out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * S) return;
+  const long long r = i / S;
+  const int c = (int)(i - r * S);
+  const int sl = c / sw;
+  out[(size_t)sl * n * sw + (size_t)r * sw + (c - sl * sw)] = X[(size_t)r * ldx + c];
+}
+
+template <class T>
+void launch_pack_slices(hipStream_t st, long long n, int S, int nslices, const T *X,
+                        long long ldx, T *out) {
+  const long long tot = n * S;
+  if (tot <= 0) return;
+  const int th = 256;
+  k_pack_slices<T><<<(unsigned)((tot + th - 1) / th), th, 0, st>>>(n, S, S / nslices, X, ldx, out);
+  check_launch("k_pack_slices");
+}
+
+template void launch_pack_slices<float>(hipStream_t, long long, int, int, const float *,
+                                        long long, float *);
+template void launch_pack_slices<double>(hipStream_t, long long, int, int, const double *,
+                                         long long, double *);
 
 template <class Tin, class Tout>
 __global__ void k_cast(long long n, int S, const Tin *in, long long ldin, Tout *out,

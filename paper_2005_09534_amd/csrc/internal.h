@@ -58,6 +58,7 @@ struct DevBuf {
 // Device-resident description of the Sz=0 basis of one chain length L:
 // states[n] ascending, and the two rank tables with
 //   rank(s) = tabA[s >> half] + tabB[s & (2^half - 1)]
+// (tabA int32, tabB uint16: a rank among at most C(15, 7) low patterns)
 // (the colexicographic rank sum_t C(p_t, t) split at bit `half`; each half
 // contributes a term that depends only on its own bits once the total
 // popcount is fixed at L/2).
@@ -78,8 +79,9 @@ struct Chain {
   DevBuf diag;  // FP64 H[r][r]
 };
 
-// Maximum L handled with the rank tables in LDS (2 * 2^(L/2) int32).
-constexpr int kMaxLdsTableL = 26;
+// Maximum L handled with the rank tables in LDS (6 * 2^(L/2) bytes: 96 KB
+// at L = 28, within the 160 KB of a CU).
+constexpr int kMaxLdsTableL = 28;
 
 // --------------------------------------------------------------- kernels --
 
@@ -102,7 +104,7 @@ struct StepArgs {
   const uint32_t *states;
   const T *dt;
   const int32_t *tabA;
-  const int32_t *tabB;
+  const uint16_t *tabB;
   const T *X;
   long long ldx;
   const T *V;
@@ -126,16 +128,25 @@ struct StepArgs {
   long long ldsrc;
   T cin, cacc;
   int skip_out;  // the step's own output is not stored (only acc is)
+  // XCD column slices (1, 2, 4 or 8): the block's S columns are split into
+  // nslices slices of S / nslices columns; the workgroups of XCD x work on
+  // slice x % nslices only, over the rows of part x / nslices.  Each operand
+  // gives the element offset from one slice to the next (a row-major block:
+  // the slice width; a slice-major block: n times the slice width) -- its
+  // leading dimension is then that of the slice.
+  int nslices;
+  long long xss, vss, wss, oss, accss, srcss;
 };
 
 // Launch shape of the step kernel (the autotuner's search space).
 struct StepShape {
-  int threads = 256;     // workgroup size (multiple of 64)
+  int threads = 256;     // workgroup size: 256, 512 or 1024
   int lpl = 1;           // 16-byte loads per lane per gathered row
   int wg_per_cu = 8;     // persistent workgroups per CU
   int lds_tables = 1;    // stage rank tables in LDS
   int early_loads = 0;   // issue the streamed loads before the gathers
   int rank_incr = 0;     // incremental ranks for bonds that do not wrap
+  int xcd_slices = 1;    // column slices, one per XCD group (1, 2, 4, 8)
 };
 
 template <class T>
@@ -160,6 +171,12 @@ void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const Batc
                          int B, long long j, long long Kmax, const StepShape &shape, int num_cu);
 // Built-in default shape (used when the context holds no tuned entry).
 StepShape default_shape(int L, int S, bool fp32);
+
+// out (slice-major: nslices blocks of n x (S / nslices), each row's slice
+// contiguous) <- X (n x S, row-major, leading dimension ldx).
+template <class T>
+void launch_pack_slices(hipStream_t st, long long n, int S, int nslices, const T *X,
+                        long long ldx, T *out);
 
 template <class Tin, class Tout>
 void launch_cast(hipStream_t st, long long n, int S, const Tin *in, long long ldin, Tout *out,
@@ -231,6 +248,11 @@ void launch_lanczos_update(hipStream_t st, long long n, double *w, const double 
                            const double *beta_prev, double *part2);
 void launch_lanczos_normalize(hipStream_t st, long long n, const double *w, double *vnext,
                               const double *part2, int nblk, double *beta);
+
+// measure.hip: copy rate (read + write bytes per second / 1e9) of a plain
+// 16-byte-vector device copy of `bytes` bytes, repeated reps times.
+double stream_copy_gbs(hipStream_t st, const void *src, void *dst, long long bytes, int reps,
+                       int num_cu);
 
 // ------------------------------------------------------------ host math --
 

@@ -54,7 +54,7 @@ static StepArgs<T> base_args(const Chain &c, const T *dt) {
   a.states = b.states.as<uint32_t>();
   a.dt = dt;
   a.tabA = b.tabA.as<int32_t>();
-  a.tabB = b.tabB.as<int32_t>();
+  a.tabB = b.tabB.as<uint16_t>();
   a.n = b.n;
   a.L = c.L;
   a.half = b.half;
@@ -62,6 +62,7 @@ static StepArgs<T> base_args(const Chain &c, const T *dt) {
   a.fullmask = (c.L >= 32) ? 0xffffffffu : ((1u << c.L) - 1u);
   a.has_j2 = (c.J2 != 0.0) ? 1 : 0;
   a.binom = b.binom.as<int32_t>();
+  a.nslices = 1;
   return a;
 }
 
@@ -185,33 +186,60 @@ static double queue_filter_forward(hipStream_t stream, int num_cu, const StepSha
 // k = K..1, then Y = (c_0 X + H~ b_1 - b_2) / D (or by the forward form,
 // per `form`).  dt = a d + b in T.  Returns the algorithmic bytes of the
 // launches it queues; with launch = false only counts them.
+// Column slices of the Clenshaw filter for this shape and width (1 when
+// the shape asks for none or the width does not split).
+static int filter_slices(const StepShape &shape, int S) {
+  const int ns = shape.xcd_slices;
+  return (ns > 1 && ns <= S && S % ns == 0) ? ns : 1;
+}
+
 template <class T>
 static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shape, const Chain &c,
                            const T *dt, double a, int S, const T *X, long long ldx, T *Y,
                            long long ldy, long long K, const std::vector<double> &coef, double D,
-                           T *buf3, int form, bool launch = true) {
+                           T *buf3, int form, T *xpack, bool launch = true) {
   if (form == POLFED_FORM_FORWARD)
     return queue_filter_forward<T>(stream, num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
                                    D, buf3, launch);
   const long long n = c.basis->n;
   T *bufs[3] = {buf3, buf3 + (size_t)n * S, buf3 + (size_t)2 * n * S};
+  // With XCD column slices the recurrence blocks and a copy of X are held
+  // slice-major (each slice an n x S/ns block), so that one XCD's rows of
+  // its slice are contiguous; only Y, written once, stays row-major.
+  const int ns = filter_slices(shape, S);
+  const long long sw = S / ns;
+  const long long bss = (ns > 1) ? n * sw : 0;  // slice stride of a packed block
+  const long long bld = (ns > 1) ? sw : S;      // its leading dimension
+  const T *Xin = X;
+  long long ldxin = ldx, xss = 0;
+  if (ns > 1) {
+    if (launch) launch_pack_slices<T>(stream, n, S, ns, X, ldx, xpack);
+    Xin = xpack;
+    ldxin = sw;
+    xss = n * sw;
+  }
   double moved = 0.0;
   for (long long j = 0; j < K; ++j) {
     const long long k = K - j;
     StepArgs<T> st = base_args<T>(c, dt);
+    st.nslices = ns;
     st.out = bufs[j % 3];
-    st.ldo = S;
+    st.ldo = bld;
+    st.oss = bss;
     if (j >= 1) {
       st.V = bufs[(j - 1) % 3];
-      st.ldv = S;
+      st.ldv = bld;
+      st.vss = bss;
     }
     if (j >= 2) {
       st.W = bufs[(j - 2) % 3];
-      st.ldw = S;
+      st.ldw = bld;
+      st.wss = bss;
     }
     if (coef[k] != 0.0) {
-      st.X = X;
-      st.ldx = ldx;
+      st.X = Xin;
+      st.ldx = ldxin;
+      st.xss = xss;
     }
     st.alpha = (T)coef[k];
     st.dscale = T(2);
@@ -222,20 +250,25 @@ static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shap
     moved += step_bytes(st, S);
   }
   StepArgs<T> st = base_args<T>(c, dt);
+  st.nslices = ns;
   st.out = Y;
   st.ldo = ldy;
-  st.X = X;
-  st.ldx = ldx;
+  st.oss = (ns > 1) ? sw : 0;
+  st.X = Xin;
+  st.ldx = ldxin;
+  st.xss = xss;
   // (products with 1/D, as in the batched kernel)
   const double Dinv = 1.0 / D;
   st.alpha = (T)(coef[0] * Dinv);
   if (K >= 1) {
     st.V = bufs[(K - 1) % 3];
-    st.ldv = S;
+    st.ldv = bld;
+    st.vss = bss;
   }
   if (K >= 2) {
     st.W = bufs[(K - 2) % 3];
-    st.ldw = S;
+    st.ldw = bld;
+    st.wss = bss;
   }
   st.dscale = (T)Dinv;
   st.w1 = (T)(0.5 * (a * c.J1) * Dinv);
@@ -266,6 +299,10 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
   }
   double moved = 0.0;
   const int form = ctx->filter_form;
+  // the slice-major copy of X (allocated before any capture)
+  T *xpack = nullptr;
+  if (form == POLFED_FORM_CLENSHAW && filter_slices(shape, S) > 1)
+    xpack = static_cast<T *>(ctx->buf("xpack").ensure(sizeof(T) * (size_t)n * S));
   // a graph pays for its capture only when it is replayed: filters run once
   // (the refinement passes, each with its own order) launch directly
   if (reused && ctx->use_graphs && graph_worthwhile<T>(n, S, K)) {
@@ -279,6 +316,7 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
         (unsigned long long)shape.threads, (unsigned long long)shape.lpl,
         (unsigned long long)shape.wg_per_cu, (unsigned long long)shape.lds_tables,
         (unsigned long long)shape.early_loads, (unsigned long long)shape.rank_incr,
+        (unsigned long long)shape.xcd_slices, (unsigned long long)(uintptr_t)xpack,
         (unsigned long long)form};
     auto bits = [](double v) {
       unsigned long long u;
@@ -306,7 +344,7 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
       PF_HIP(hipStreamBeginCapture(ctx->own_stream, hipStreamCaptureModeThreadLocal));
       try {
         queue_filter<T>(ctx->own_stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
-                        D, buf3, form);
+                        D, buf3, form, xpack);
       } catch (...) {
         hipGraph_t dummy = nullptr;
         (void)hipStreamEndCapture(ctx->own_stream, &dummy);
@@ -323,11 +361,11 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
     PF_HIP(hipGraphLaunch(ctx->filter_graph, ctx->stream));
     // same byte model as the direct path
     moved = queue_filter<T>(ctx->own_stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K,
-                            coef, D, buf3, form, false);
+                            coef, D, buf3, form, xpack, false);
   } else {
     PF_HIP(hipEventRecord(ctx->ev_start, ctx->stream));
     moved = queue_filter<T>(ctx->stream, ctx->num_cu, shape, c, dt, a, S, X, ldx, Y, ldy, K, coef,
-                            D, buf3, form);
+                            D, buf3, form, xpack);
   }
   if (bytes) *bytes += moved;
   PF_HIP(hipEventRecord(ctx->ev_stop, ctx->stream));
@@ -1558,11 +1596,15 @@ template void stage_apply_filter<double>(polfed_ctx *, const Chain &, double, do
 
 StepShape default_shape(int L, int S, bool fp32) {
   // From sweeps of (threads, loads per lane, groups per CU, LDS tables,
-  // early streamed loads) on gfx950 boxes: eight 256-thread groups per CU
-  // with the rank tables in LDS lead throughout; short rows (L <= 16, and
-  // FP32 at L = 18) want one 16-byte load per lane, the rest two; FP32 at
-  // L >= 22 prefers two 1024-thread groups per CU.  Short chains (L <= 16)
-  // sit near the launch floor (~5-6 us a step).
+  // early streamed loads, column slices) on gfx950 boxes: eight 256-thread
+  // groups per CU with the rank tables in LDS lead up to L = 20; short rows
+  // (L <= 16, and FP32 at L = 18) want one 16-byte load per lane, the rest
+  // two; FP32 at L = 22 prefers two 1024-thread groups per CU.  At L >= 22
+  // splitting the block's columns over the XCDs pays in FP64 (L = 22: two
+  // slices, 231 against 244 us a step at s = 32; L = 26: four slices, 9.4
+  // against 10.4 ms at s = 64) and at L = 26 in FP32 (two slices, 4.46
+  // against 4.63 ms at s = 64).  Short chains (L <= 16) sit near the launch
+  // floor (~5-6 us a step).
   StepShape sh;
   sh.lds_tables = 1;
   sh.lpl = 2;
@@ -1570,9 +1612,21 @@ StepShape default_shape(int L, int S, bool fp32) {
   sh.wg_per_cu = 8;
   if (L <= 16 || (L == 18 && fp32)) {
     sh.lpl = 1;
+  } else if (L >= 24 && fp32) {
+    sh.threads = 512;
+    sh.wg_per_cu = 2;
+    sh.xcd_slices = 2;
+  } else if (L >= 24) {
+    sh.wg_per_cu = 2;
+    sh.xcd_slices = 4;
   } else if (L >= 22 && fp32) {
     sh.threads = 1024;
     sh.wg_per_cu = 2;
+  } else if (L >= 22) {
+    sh.threads = 512;
+    sh.wg_per_cu = 4;
+    sh.early_loads = 1;
+    sh.xcd_slices = 2;
   }
   (void)S;
   return sh;

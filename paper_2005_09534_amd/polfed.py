@@ -96,12 +96,13 @@ def _load():
         "polfed_bounds": (c_int, [c_void_p, ctypes.POINTER(Model), c_int, c_ull, P_double,
                                   P_double, P_double, P_double]),
         "polfed_set_step_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int,
-                                          c_int, c_int, c_int]),
-        "polfed_get_step_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 6),
+                                          c_int, c_int, c_int, c_int]),
+        "polfed_get_step_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 7),
         "polfed_set_graphs": (c_int, [c_void_p, c_int]),
         "polfed_set_filter_form": (c_int, [c_void_p, c_int]),
         "polfed_set_block_size": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
         "polfed_filter_stats": (c_int, [c_void_p, P_double, P_double, P_double, c_int]),
+        "polfed_stream_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_ll, c_int, P_double]),
         "polfed_solve": (c_int, [c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts), c_int,
                                  P_double, P_double, P_double, ctypes.POINTER(Info)]),
         "polfed_solve_batch": (c_int, [c_void_p, c_int, ctypes.POINTER(Model),
@@ -285,15 +286,15 @@ class Context:
 
     # ---- tuning / measurement ----
     def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1,
-                       early_loads=0, rank_incremental=0):
+                       early_loads=0, rank_incremental=0, xcd_slices=1):
         self._check(LIB.polfed_set_step_shape(self.h, L, nvec, precision, threads, lpl, wg_per_cu,
                                               int(lds_tables), int(early_loads),
-                                              int(rank_incremental)),
+                                              int(rank_incremental), int(xcd_slices)),
                     "set_step_shape")
 
     def get_step_shape(self, L, nvec, precision):
-        """(threads, lpl, wg_per_cu, lds_tables, early_loads, rank_incremental)."""
-        out = [c_int() for _ in range(6)]
+        """(threads, lpl, wg_per_cu, lds_tables, early_loads, rank_incremental, xcd_slices)."""
+        out = [c_int() for _ in range(7)]
         self._check(LIB.polfed_get_step_shape(self.h, L, nvec, precision,
                                               *[ctypes.byref(o) for o in out]), "get_step_shape")
         return tuple(o.value for o in out)
@@ -314,6 +315,17 @@ class Context:
         self._check(LIB.polfed_filter_stats(self.h, ctypes.byref(g), ctypes.byref(l),
                                             ctypes.byref(b), int(reset)), "filter_stats")
         return dict(gpu_s=g.value, launches=l.value, bytes=b.value)
+
+    def stream_copy(self, src, dst, reps=10):
+        """Copy rate (GB/s, read + write) of the library's plain copy kernel
+        from tensor src to tensor dst (same byte size)."""
+        gbs = c_double()
+        nbytes = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != nbytes:
+            raise ValueError("src and dst must have the same byte size")
+        self._check(LIB.polfed_stream_copy(self.h, _ptr(src), _ptr(dst), nbytes, reps,
+                                           ctypes.byref(gbs)), "stream_copy")
+        return gbs.value
 
     # ---- the solve (host outputs) ----
     def solve(self, model, nev, opts=None, vectors=True, **kw):

@@ -10,9 +10,9 @@ class _FakeCtx:
         self.calls = []
 
     def set_step_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1, early_loads=0,
-                       rank_incremental=0):
+                       rank_incremental=0, xcd_slices=1):
         self.calls.append(("shape", L, nvec, precision, threads, lpl, wg_per_cu, lds_tables,
-                           early_loads, rank_incremental))
+                           early_loads, rank_incremental, xcd_slices))
 
     def set_block_size(self, L, precision, nev, block_size):
         self.calls.append(("block", L, precision, nev, block_size))
@@ -20,17 +20,28 @@ class _FakeCtx:
 
 def test_shape_candidates_are_valid():
     assert len(autotune.SHAPES) == len(set(autotune.SHAPES))
-    for t, lpl, wpc, lds, early, ranki in autotune.SHAPES:
-        assert t in (256, 1024) and lpl in (1, 2, 4) and lds in (0, 1) and early in (0, 1)
-        assert ranki in (0, 1) and wpc >= 1
+    for t, lpl, wpc, lds, early, ranki, xcd in autotune.SHAPES:
+        assert t in (256, 512, 1024) and lpl in (1, 2, 4) and lds in (0, 1) and early in (0, 1)
+        assert ranki in (0, 1) and wpc >= 1 and xcd in (1, 2, 4, 8)
     assert {sh[5] for sh in autotune.SHAPES} == {0, 1}
+    assert {sh[6] for sh in autotune.SHAPES} == {1, 2, 4, 8}
+
+
+def test_staged_candidates_split_the_width():
+    best = (256, 2, 8, 1, 0, 1, 1)
+    for width in (1, 2, 4, 64):
+        c = autotune.staged_candidates(best, width)
+        assert all(sh[3:6] == best[3:6] and 2 <= sh[6] <= width for sh in c)
+        assert {sh[6] for sh in c} == {x for x in (2, 4, 8) if x <= width}
+        assert len(c) == len(set(c))
 
 
 def test_cache_round_trip_and_apply(tmp_path):
-    # the second shape entry is in the older five-field form (no rank mode)
+    # older entries: six fields (no column slices), five (no rank mode)
     cache = {autotune._key("shape", 18, 0.0, 1, 32): [1024, 2, 2, 1, 0, 1, 2500.0],
              autotune._key("block", 18, 0.0, 1, 20): [8, 0.5],
-             autotune._key("shape", 22, 1.0, 0, 16): [256, 1, 4, 0, 1, 1800.0]}
+             autotune._key("shape", 22, 1.0, 0, 16): [256, 1, 4, 0, 1, 1800.0],
+             autotune._key("shape", 26, 0.0, 1, 64): [1024, 2, 2, 1, 0, 0, 8, 4000.0]}
     path = tmp_path / "tune.json"
     autotune.save_cache(cache, str(path))
     assert json.loads(path.read_text()) == cache
@@ -38,9 +49,10 @@ def test_cache_round_trip_and_apply(tmp_path):
     assert back == cache
     ctx = _FakeCtx()
     autotune.apply_cache(ctx, back)
-    assert sorted(ctx.calls) == sorted([("shape", 18, 32, 1, 1024, 2, 2, 1, 0, 1),
+    assert sorted(ctx.calls) == sorted([("shape", 18, 32, 1, 1024, 2, 2, 1, 0, 1, 1),
                                         ("block", 18, 1, 20, 8),
-                                        ("shape", 22, 16, 0, 256, 1, 4, 0, 1, 0)])
+                                        ("shape", 22, 16, 0, 256, 1, 4, 0, 1, 0, 1),
+                                        ("shape", 26, 64, 1, 1024, 2, 2, 1, 0, 0, 8)])
 
 
 def test_missing_cache_is_empty(tmp_path):

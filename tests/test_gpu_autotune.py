@@ -38,10 +38,12 @@ def test_shapes_bitwise_identical(ctx, precision, width, J2):
     w = E1 - E0
     E0w, E1w = E0 - r0 - 1e-3 * w, E1 + r1 + 1e-3 * w
     ref = None
-    early = [sh for sh in autotune.SHAPES if sh[4] == 1]
-    ranki = [sh for sh in autotune.SHAPES if sh[5] == 1]
-    assert early and ranki
-    for sh in autotune.SHAPES[::3] + early[::2] + ranki[::5]:
+    unsliced = [sh for sh in autotune.SHAPES if sh[6] == 1]
+    early = [sh for sh in unsliced if sh[4] == 1]
+    ranki = [sh for sh in unsliced if sh[5] == 1]
+    sliced = [sh for sh in autotune.SHAPES if sh[6] > 1 and sh[6] <= width]
+    assert early and ranki and (sliced or width == 1)
+    for sh in unsliced[::3] + early[::2] + ranki[::5] + sliced[::7]:
         ctx.set_step_shape(c.L, width, precision, *sh)
         Y = ctx.apply_filter(m, E0w, E1w, 0.0, 40, X)
         torch.cuda.synchronize()
@@ -99,6 +101,7 @@ def test_get_step_shape_reports_what_is_in_force(ctx):
     ctx.set_step_shape(20, 8, 1, *sh)
     assert ctx.get_step_shape(20, 8, 1) == tuple(sh)
     d = ctx.get_step_shape(20, 8, 0)  # untouched entry: the built-in default
-    assert len(d) == 6 and d[0] in (256, 1024) and d[1] in (1, 2, 4) and d[2] >= 1
-    ctx.set_step_shape(20, 8, 1, 256, 2, 8)  # trailing fields default to 1, 0, 0
-    assert ctx.get_step_shape(20, 8, 1) == (256, 2, 8, 1, 0, 0)
+    assert len(d) == 7 and d[0] in (256, 1024) and d[1] in (1, 2, 4) and d[2] >= 1
+    assert d[6] in (1, 2, 4, 8)
+    ctx.set_step_shape(20, 8, 1, 256, 2, 8)  # trailing fields default to 1, 0, 0, 1
+    assert ctx.get_step_shape(20, 8, 1) == (256, 2, 8, 1, 0, 0, 1)
