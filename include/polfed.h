@@ -82,6 +82,12 @@ typedef struct {
   double eta;             /* bounds margin, fraction of E1-E0; 0 -> 1e-3   */
   int bounds_steps;       /* bounds Lanczos steps; 0 -> 200                 */
   unsigned long long seed;/* start-block generator key                     */
+  long long max_order;    /* FP32 filter with automatic K: the largest order
+                             it may take (0 -> 200000); beyond it the
+                             window is widened until K fits (N_ev -> a N_ev
+                             gives K -> K/a at about the same filter work;
+                             Supplement, "Benchmark for disorder spin
+                             chains"), and info->nev_window reports it    */
 } polfed_opts;
 
 /* Per-solve record (all times in seconds, wall clock on the host). */
@@ -146,6 +152,14 @@ int polfed_cheb_coeffs(double sigma_tilde, long long K, double *c, double *D);
 int polfed_filter_order(const polfed_model *model, double E0w, double E1w,
                         double sigma_tilde, int nwin, double p,
                         long long *K, double *rho);
+
+/* The order cap of the FP32 filter (polfed_opts.max_order): the smallest
+ * window count *nwin_out >= nwin whose order from polfed_filter_order is at
+ * most max_order, and that order *K (max_order <= 0: no cap, the window
+ * stays nwin).  The window never exceeds the sector size. */
+int polfed_window_order(const polfed_model *model, double E0w, double E1w,
+                        double sigma_tilde, int nwin, double p, long long max_order,
+                        int *nwin_out, long long *K);
 
 /* ---- stage calls (device pointers, async on the context stream) -------- */
 

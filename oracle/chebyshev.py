@@ -172,3 +172,19 @@ def choose_K(nev, sigma, p, N, Ebar, Gamma, E0, E1, K_max=1 << 26):
         else:
             hi = mid
     return lo
+
+
+def capped_window(nwin, sigma, p, N, Ebar, Gamma, E0, E1, K_cap):
+    """Window count under a cap on the order (the FP32 filter's rounding
+    error grows like sqrt(K)): the smallest N_win >= nwin whose order
+    choose_K(N_win) is at most K_cap, found by scanning upward.  A wider
+    window takes a shorter filter at about the same total work (Supplement,
+    "Benchmark for disorder spin chains": N_ev -> a N_ev gives K -> K/a).
+    Returns (N_win, K).  Parity: pinned by its definition (the order fits,
+    one fewer does not) and by the paper's K ~ 1/N_win law."""
+    w = int(nwin)
+    while True:
+        K = choose_K(w, sigma, p, N, Ebar, Gamma, E0, E1)
+        if K <= K_cap or w >= N:
+            return w, K
+        w += 1

@@ -109,6 +109,7 @@ void polfed_default_opts(polfed_opts *o) {
   o->eta = 1e-3;
   o->bounds_steps = 200;
   o->seed = 12345;
+  o->max_order = 0;
 }
 
 // Message of the last failed polfed_create on this host thread (there is no
@@ -203,6 +204,20 @@ int polfed_filter_order(const polfed_model *m, double E0w, double E1w, double si
   double r = 0.0;
   *K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, p, &r);
   if (rho) *rho = r;
+  return POLFED_OK;
+}
+
+int polfed_window_order(const polfed_model *m, double E0w, double E1w, double sigma, int nwin,
+                        double p, long long max_order, int *nwin_out, long long *K) {
+  if (!m || !m->h || !K || !nwin_out || nwin < 1 || !(E1w > E0w) || !(std::fabs(sigma) < 1.0) ||
+      !(p > 0.0))
+    return POLFED_EINVAL;
+  long long n = polfed_dim(m->L);
+  if (n < 0) return POLFED_EINVAL;
+  const double Gamma = dos_gamma(m->L, m->J1, m->J2, m->Delta, m->h);
+  const double Ebar = trace_mean(m->L, m->J1, m->J2, m->Delta);
+  *nwin_out = capped_window(n, Ebar, Gamma, E0w, E1w, sigma, (int)std::min<long long>(nwin, n), p,
+                            max_order, K);
   return POLFED_OK;
 }
 

@@ -262,6 +262,8 @@ double dos_gamma(int L, double J1, double J2, double Delta, const double *h);
 double trace_mean(int L, double J1, double J2, double Delta);
 long long choose_order(long long N, double Ebar, double Gamma, double E0w, double E1w,
                        double sigma, int nwin, double p, double *rho);
+int capped_window(long long N, double Ebar, double Gamma, double E0w, double E1w, double sigma,
+                  int nwin, double p, long long K_cap, long long *K);
 // Extreme eigenvalues of the symmetric tridiagonal (alpha[k], beta[k] for
 // k=1..k-1 off-diagonal) and the last components of their unit
 // eigenvectors.

@@ -122,6 +122,39 @@ long long choose_order(long long N, double Ebar, double Gamma, double E0w, doubl
   return lo;
 }
 
+// The smallest window count N >= nwin whose order K(N) = choose_order(N)
+// does not exceed K_cap (K_cap <= 0: no cap, N = nwin).  K(N) falls as N
+// grows (a wider window needs a shorter filter: N_ev -> alpha N_ev gives
+// K -> K / alpha at about the same total filter work; Supplement,
+// "Benchmark for disorder spin chains"), so N is found by doubling and
+// bisection; it is at most the sector size.  Writes that order to *K.
+int capped_window(long long N, double Ebar, double Gamma, double E0w, double E1w, double sigma,
+                  int nwin, double p, long long K_cap, long long *K) {
+  auto order = [&](long long w) {
+    return choose_order(N, Ebar, Gamma, E0w, E1w, sigma, (int)w, p, nullptr);
+  };
+  long long k = order(nwin);
+  if (K_cap <= 0 || k <= K_cap || nwin >= N) {
+    *K = k;
+    return nwin;
+  }
+  long long lo = nwin, hi = nwin;  // order(lo) > K_cap
+  for (;;) {
+    hi = std::min<long long>(N, 2 * hi);
+    if (order(hi) <= K_cap || hi == N) break;
+    lo = hi;
+  }
+  while (hi - lo > 1) {
+    const long long mid = (lo + hi) / 2;
+    if (order(mid) <= K_cap)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  *K = order(hi);
+  return (int)hi;
+}
+
 // ---- tridiagonal extremes (bounds Lanczos) --------------------------------
 
 // number of eigenvalues < x of the tridiagonal (a[0..m), b[1..m) off-diag)

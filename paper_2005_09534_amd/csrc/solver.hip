@@ -509,6 +509,10 @@ constexpr double kFp32ResidBar = 1e-8;
 // Widest filter window (in units of N_ev) the solve grows to when the
 // Gaussian DOS has sized it too narrow: the default 1.5 doubled three times.
 constexpr double kMaxWindowFactor = 12.0;
+// Largest automatic filter order of the FP32 filter: its rounding error
+// relative to the FP64 filter, measured at about 3.5 eps32 sqrt(K) with
+// eps32 = 2^-24, stays below 1e-4 up to K ~ 2.3e5; 2e5 keeps a margin.
+constexpr long long kFp32MaxOrder = 200000;
 
 template <class T>
 struct Realization {
@@ -530,6 +534,9 @@ struct Realization {
   DevBuf Vprevb, thprevb, Wb;
   int ms_prev = 0;
   int m_done = 0, nconv = 0, refills = 0;
+  // batch member that failed with an error of its own (bounds, breakdown,
+  // invalid target): its status, and it takes no further part
+  int err = 0;
   int above = 0;  // Ritz values with theta >= p at the last convergence check
   bool done = false;
   double t_start = 0, t_bounds = 0, t_filter = 0, t_orth = 0, t_eig = 0, bytes = 0;
@@ -608,11 +615,28 @@ void Realization<T>::setup(polfed_ctx *ctx_, const polfed_model *model, const po
     const double Gamma = dos_gamma(c.L, c.J1, c.J2, c.Delta, c.h);
     const double Ebar = trace_mean(c.L, c.J1, c.J2, c.Delta);
     K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, &rho);
+    // FP32 filter: its rounding error grows like eps32 sqrt(K); beyond the
+    // cap the window is widened until K fits (the wider window then counts
+    // as one wider than the default for the stop rule)
+    const long long cap = (o.max_order > 0) ? o.max_order : kFp32MaxOrder;
+    if (fp32 && K > cap) {
+      nwin = capped_window(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, cap, &K);
+      o.window_factor = std::max(o.window_factor, (double)nwin / nev);
+    }
   }
   cheb_coeffs(sigma, K, coef, D);
-  // column cap: 8 N_win + 8 s in whole blocks, at most n
+  // column cap: 8 N_win + 8 s in whole blocks, at most n, and the Lanczos
+  // basis within half of the device memory free now (the Rayleigh-Ritz
+  // step needs room for three more blocks of the candidates' width)
   long long cols = (o.max_cols > 0) ? o.max_cols : 8LL * nwin + 8LL * s;
   cols = std::min<long long>(cols, (n / s) * s);
+  {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
+      const long long cols_mem = ((long long)(0.5 * (double)free_b / (8.0 * (double)n)) / s) * s;
+      if (cols_mem >= s) cols = std::min(cols, cols_mem);
+    }
+  }
   m_max = (int)std::max<long long>(1, cols / s);
   P = m_max * s;
   // convergence threshold on ||B t~||: FP64 filter 1e-10; FP32 filter
@@ -1178,9 +1202,10 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
 template <class T>
 static int solve_single(polfed_ctx *ctx, const polfed_model *model, const polfed_opts &o, int nev,
                         double *evals, double *evecs, double *resid, polfed_info *info,
-                        bool *short_window = nullptr) {
+                        bool *short_window = nullptr, double *window_factor_used = nullptr) {
   Realization<T> R;
   R.setup(ctx, model, o, nev);
+  if (window_factor_used) *window_factor_used = R.o.window_factor;
   T *cheb = static_cast<T *>(ctx->buf("cheb").ensure(sizeof(T) * 3 * (size_t)R.n * R.s));
   while (!R.done) {
     const double t0 = now_s();
@@ -1230,7 +1255,9 @@ static int solve_widened(polfed_ctx *ctx, const polfed_model *model, polfed_opts
   bool have_prev = false;
   for (;;) {
     bool short_window = false;
-    int rc = solve_single<T>(ctx, model, o, nev, evals, evecs, resid, info, &short_window);
+    double wf = o.window_factor;
+    int rc = solve_single<T>(ctx, model, o, nev, evals, evecs, resid, info, &short_window, &wf);
+    o.window_factor = wf;  // the FP32 order cap may have widened it
     if (have_prev) add_attempt(*info, prev);
     if (!short_window) return rc;
     if (2.0 * o.window_factor > kMaxWindowFactor)
@@ -1292,27 +1319,47 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
     validate_model(&models[r]);
     PF_REQUIRE(nev >= 1 && nev <= polfed_dim(models[r].L), "nev must be in [1, dim] for every model");
   }
-  // group by (L, block size)
-  std::map<std::pair<int, int>, std::vector<int>> groups;
+  // group by (L, block size, J2 != 0): the batched kernel takes the bond
+  // ranges of the group from one member, so a group must agree on them
+  std::map<std::tuple<int, int, int>, std::vector<int>> groups;
   for (int r = 0; r < R; ++r) {
     const int s = o.block_size ? o.block_size : block_for(ctx, models[r].L, nev, o.precision);
-    groups[{models[r].L, s}].push_back(r);
+    groups[std::make_tuple(models[r].L, s, models[r].J2 != 0.0 ? 1 : 0)].push_back(r);
   }
   int worst = POLFED_OK;
+  // errors that belong to one realisation end that member only; the others
+  // complete (errors of the device or its memory end the call)
+  auto member_error = [](const Error &e) {
+    return e.code == POLFED_EBOUNDS || e.code == POLFED_EBREAKDOWN || e.code == POLFED_EINVAL;
+  };
   for (auto &g : groups) {
     const std::vector<int> &mem = g.second;
     const int B = (int)mem.size();
     const double tg0 = now_s();
     std::vector<std::unique_ptr<Realization<T>>> rs(B);
     polfed_opts og = o;
-    og.block_size = g.first.second;
+    og.block_size = std::get<1>(g.first);
     long long Kmax = 0;
+    int first_ok = -1;
     for (int i = 0; i < B; ++i) {
       rs[i].reset(new Realization<T>());
-      rs[i]->setup(ctx, &models[mem[i]], og, nev);
+      try {
+        rs[i]->setup(ctx, &models[mem[i]], og, nev);
+      } catch (const Error &e) {
+        if (!member_error(e)) throw;
+        rs[i]->err = e.code;
+        rs[i]->done = true;
+        continue;
+      }
       Kmax = std::max(Kmax, rs[i]->K);
+      if (first_ok < 0) first_ok = i;
     }
-    const Realization<T> &r0 = *rs[0];
+    if (first_ok < 0) {  // every member of the group failed in its setup
+      for (int i = 0; i < B; ++i) status[mem[i]] = rs[i]->err;
+      if (worst == POLFED_OK) worst = POLFED_NOT_CONVERGED;
+      continue;
+    }
+    const Realization<T> &r0 = *rs[first_ok];
     const long long n = r0.n;
     const int S = r0.s;
     // per-member recurrence buffers, coefficients and descriptors
@@ -1337,7 +1384,7 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
       it.w1 = (T)(r.a * r.c.J1);
       it.w2 = (T)(r.a * r.c.J2);
       it.K = r.K;
-      it.active = 1;
+      it.active = r.err ? 0 : 1;
       co += r.coef.size();
     }
     itemsd.ensure(sizeof(BatchItem<T>) * B);
@@ -1414,8 +1461,16 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
         // members advance in lock step, so the checks share one size and
         // their eigenproblems run in one batched launch when small enough
         std::vector<int> due;
-        for (int i = 0; i < B; ++i)
-          if (items[i].active && rs[i]->lanczos_block()) due.push_back(i);
+        for (int i = 0; i < B; ++i) {
+          if (!items[i].active) continue;
+          try {
+            if (rs[i]->lanczos_block()) due.push_back(i);
+          } catch (const Error &e) {
+            if (!member_error(e)) throw;
+            rs[i]->err = e.code;
+            rs[i]->done = true;
+          }
+        }
         if (!due.empty()) {
           const int msz = rs[due[0]]->check_size();
           bool same = true;
@@ -1459,6 +1514,11 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
     const bool can_widen = 2.0 * og.window_factor <= kMaxWindowFactor;
     for (int i = 0; i < B; ++i) {
       const int r = mem[i];
+      if (rs[i]->err) {  // outputs of a failed member stay untouched
+        status[r] = rs[i]->err;
+        if (worst == POLFED_OK) worst = POLFED_NOT_CONVERGED;
+        continue;
+      }
       rs[i]->filter_gpu_s = gfilter / B;
       rs[i]->filter_launches = glaunch / B;
       polfed_info ir;
@@ -1538,7 +1598,7 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
       fprintf(stderr,
               "[polfed] batch group L=%d s=%d: %d members, Lanczos %.2f s (filter kernels "
               "%.2f s), finalize %.2f s\n",
-              g.first.first, g.first.second, B, tg1 - tg0, gfilter, now_s() - tg1);
+              std::get<0>(g.first), std::get<1>(g.first), B, tg1 - tg0, gfilter, now_s() - tg1);
   }
   return worst;
 }

@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("target_kind", c_int), ("target", c_double), ("block_size", c_int),
                 ("K", c_ll), ("p", c_double), ("precision", c_int),
                 ("window_factor", c_double), ("max_cols", c_int), ("tol", c_double),
-                ("eta", c_double), ("bounds_steps", c_int), ("seed", c_ull)]
+                ("eta", c_double), ("bounds_steps", c_int), ("seed", c_ull),
+                ("max_order", c_ll)]
 
 
 class Info(ctypes.Structure):
@@ -81,6 +82,8 @@ def _load():
         "polfed_cheb_coeffs": (c_int, [c_double, c_ll, P_double, P_double]),
         "polfed_filter_order": (c_int, [ctypes.POINTER(Model), c_double, c_double, c_double, c_int,
                                         c_double, ctypes.POINTER(c_ll), P_double]),
+        "polfed_window_order": (c_int, [ctypes.POINTER(Model), c_double, c_double, c_double, c_int,
+                                        c_double, c_ll, ctypes.POINTER(c_int), ctypes.POINTER(c_ll)]),
         "polfed_basis": (c_int, [c_void_p, c_int, c_void_p]),
         "polfed_rank": (c_int, [c_void_p, c_int, c_ll, c_void_p, c_void_p]),
         "polfed_diag": (c_int, [c_void_p, ctypes.POINTER(Model), c_void_p]),
@@ -166,6 +169,17 @@ def filter_order(model, E0w, E1w, sigma, nwin, p=0.17):
     if rc != OK:
         raise PolfedError(rc, "polfed_filter_order")
     return K.value, rho.value
+
+
+def window_order(model, E0w, E1w, sigma, nwin, max_order, p=0.17):
+    """(window count, K) of the FP32 order cap (polfed_window_order)."""
+    nw = c_int()
+    K = c_ll()
+    rc = LIB.polfed_window_order(ctypes.byref(model), E0w, E1w, sigma, nwin, p, max_order,
+                                 ctypes.byref(nw), ctypes.byref(K))
+    if rc != OK:
+        raise PolfedError(rc, "polfed_window_order")
+    return nw.value, K.value
 
 
 def _ptr(t):
@@ -346,8 +360,8 @@ class Context:
         o = opts if opts is not None else default_opts(**kw)
         R = len(models)
         arr = (Model * R)(*models)
-        ev = np.empty((R, nev))
-        rs = np.empty((R, nev))
+        ev = np.full((R, nev), np.nan)  # a member that fails leaves its rows untouched
+        rs = np.full((R, nev), np.nan)
         tot = sum(dim(m.L) for m in models)
         V = np.empty(tot * nev) if vectors else None
         infos = (Info * R)()

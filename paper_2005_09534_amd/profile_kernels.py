@@ -1,20 +1,21 @@
 """Profiling driver for the Chebyshev step kernel (run under rocprofv3).
 
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -o fetch -- \
-        python -m paper_2005_09534_amd.profile_kernels run --workload c2 --shape SHAPE
+        python -m paper_2005_09534_amd.profile_kernels run --workload c5 --shape SHAPE
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT -o write -- \
-        python -m paper_2005_09534_amd.profile_kernels run --workload c2 --shape SHAPE
-    python -m paper_2005_09534_amd.profile_kernels summarize --workload c2 --shape SHAPE \
+        python -m paper_2005_09534_amd.profile_kernels run --workload c5 --shape SHAPE
+    python -m paper_2005_09534_amd.profile_kernels summarize --workload c5 --shape SHAPE \
         --fetch OUT/.../fetch_counter_collection.csv --write OUT/.../write_counter_collection.csv \
-        > profiles/k_step_c2_traffic.txt
+        > profiles/k_step_c5_traffic.txt
 
 SHAPE is the step shape bench.py ran with (its config.step_shape, comma
 separated), so that the counters describe the launches the bench times.
 
 ``run`` applies the workload's filter (its chain, block width and precision)
-for a fixed number of steps, then copies a buffer of known size with a plain
-device-to-device copy kernel, whose counter readings calibrate the byte
-counts.  ``summarize`` turns the two counter CSVs into HBM bytes per step
+for a fixed number of steps, then copies a buffer of known size with the
+library's plain copy kernel (k_stream_copy, 16-byte loads and stores), whose
+counter readings calibrate the byte counts.  Workload c5 is the L = 26 chain
+with the FP64 filter (the bench's default line), c5_fp32 the same with FP32.  ``summarize`` turns the two counter CSVs into HBM bytes per step
 launch and records the hash of the kernel source the counters were taken on.
 """
 
@@ -28,27 +29,37 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30
 
 
+STEP_SOURCES = ("hv_kernels.h", "hv.hip", "hv_f32.hip")
+
+
 def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_2005_09534_amd", "csrc", "hv.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2005_09534_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _workload(name):
+    """(workload, precision name) of a profile name."""
     from paper_2005_09534_amd import workloads
-    return {"c1": workloads.c1, "c2": workloads.c2, "c3_fp64": lambda: workloads.c3("fp64"),
-            "c3_fp32": lambda: workloads.c3("fp32"), "c5": workloads.c5}[name]()
+    wl = {"c1": workloads.c1, "c2": workloads.c2, "c3_fp64": lambda: workloads.c3("fp64"),
+          "c3_fp32": lambda: workloads.c3("fp32"), "c5": workloads.c5,
+          "c5_fp32": workloads.c5}[name]()
+    prec = "fp64" if name == "c5" else wl.precision
+    return wl, prec
 
 
 def run(args):
     import torch
     from paper_2005_09534_amd import polfed as pf
-    wl = _workload(args.workload)
+    wl, precision = _workload(args.workload)
     c = wl.chains[0]
     ctx = pf.Context(0)
     m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
     n = pf.dim(c.L)
     s = wl.block if wl.block > 0 else 16
-    dt = torch.float32 if wl.precision == "fp32" else torch.float64
+    dt = torch.float32 if precision == "fp32" else torch.float64
     # the operator of the solve: Lanczos bounds widened as the solver does,
     # target at the workload's rescaled energy
     E0, E1, r0, r1 = ctx.bounds(m, 200)
@@ -59,16 +70,19 @@ def run(args):
     X = torch.randn((n, s), device="cuda", dtype=torch.float64).to(dt)
     Y = torch.empty_like(X)
     if args.shape:
-        ctx.set_step_shape(c.L, s, 1 if wl.precision == "fp32" else 0,
+        ctx.set_step_shape(c.L, s, 1 if precision == "fp32" else 0,
                            *[int(v) for v in args.shape.split(",")])
     ctx.set_graphs(False)  # one dispatch per step, each counted
     ctx.apply_filter(m, E0w, E1w, sigma, args.K, X, out=Y)
     torch.cuda.synchronize()
     st = ctx.filter_stats(reset=True)
-    # calibration: a plain copy of COPY_BYTES bytes
+    # calibration: the library's plain copy of COPY_BYTES bytes (a warm-up
+    # copy and one timed copy, both counted)
+    del X, Y
+    torch.cuda.empty_cache()
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    ctx.stream_copy(a, b, reps=1)
     torch.cuda.synchronize()
     print(f"filter: {st['launches']:.0f} launches, {st['bytes'] / st['launches']:.0f} algorithmic "
           f"bytes/launch, {1e6 * st['gpu_s'] / st['launches']:.2f} us/launch (HIP events)")
@@ -88,16 +102,18 @@ def _read(path, counter, step_name):
             v = float(row.get("Counter_Value") or 0.0)
             if step_name in name:
                 step.append(v)
-            elif "copyBuffer" in name:
+            elif "k_stream_copy" in name:
                 copy.append(v)
     return step, (max(copy) if copy else 0.0)
 
 
 def summarize(args):
-    wl = _workload(args.workload)
-    T = "float" if wl.precision == "fp32" else "double"
+    wl, precision = _workload(args.workload)
+    T = "float" if precision == "fp32" else "double"
     s = wl.block if wl.block > 0 else 16
-    step_name = f"k_step<{T}, {s},"
+    shape = [int(v) for v in args.shape.split(",")]
+    slices = shape[6] if len(shape) > 6 and s % shape[6] == 0 else 1
+    step_name = f"k_step<{T}, {s // slices},"  # the kernel's width is one slice
     fs, fc = _read(args.fetch, "FETCH_SIZE", step_name)
     ws, wc = _read(args.write, "WRITE_SIZE", step_name)
     if not fs or not ws or not fc or not wc:
@@ -130,7 +146,8 @@ def main():
     r = sub.add_parser("run")
     r.add_argument("--workload", default="c2")
     r.add_argument("--K", type=int, default=64)
-    r.add_argument("--shape", default="", help="threads,lpl,wg_per_cu,lds_tables,early_loads")
+    r.add_argument("--shape", default="",
+                   help="threads,lpl,wg_per_cu,lds_tables,early_loads,rank_incremental,xcd_slices")
     s = sub.add_parser("summarize")
     s.add_argument("--workload", default="c2")
     s.add_argument("--fetch", required=True)

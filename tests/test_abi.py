@@ -78,6 +78,27 @@ def test_filter_order_matches_oracle(L, W, J2, nwin, sigma):
     assert abs(rho - chebyshev.rho_tilde(sigma, N, Ebar, G, E0w, E1w)) < 1e-9 * rho
 
 
+@pytest.mark.parametrize("L,W,nwin,cap", [(12, 3.0, 20, 120), (12, 1.0, 10, 60), (14, 2.0, 30, 400)])
+def test_fp32_order_cap_matches_oracle(L, W, nwin, cap):
+    """The FP32 order cap: the library's window (doubling and bisection) is
+    the oracle's (upward scan), window and order integer-exact; the order
+    fits, one window fewer does not."""
+    c = workloads.chain(L, W, 11)
+    m = pf.make_model(L, c.J1, c.J2, c.Delta, c.h)
+    E0w, E1w = -0.9 * L, 0.85 * L
+    K0, _ = pf.filter_order(m, E0w, E1w, 0.0, nwin)
+    assert K0 > cap  # the cases exercise the cap
+    nw, K = pf.window_order(m, E0w, E1w, 0.0, nwin, cap)
+    N = comb(L, L // 2)
+    Ebar = -(c.J1 + c.J2) * c.Delta * L / (4.0 * (L - 1))
+    G = chebyshev.dos_gamma(L, c.J1, c.J2, c.Delta, c.h)
+    assert (nw, K) == chebyshev.capped_window(nwin, 0.0, 0.17, N, Ebar, G, E0w, E1w, cap)
+    assert K <= cap < pf.filter_order(m, E0w, E1w, 0.0, nw - 1)[0]
+    # no cap, or a cap above the order: the window stays
+    assert pf.window_order(m, E0w, E1w, 0.0, nwin, 0) == (nwin, K0)
+    assert pf.window_order(m, E0w, E1w, 0.0, nwin, K0) == (nwin, K0)
+
+
 def test_create_without_device_fails_cleanly():
     import torch
     if torch.cuda.is_available():

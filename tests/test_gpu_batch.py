@@ -161,3 +161,45 @@ def test_narrow_window_is_widened(ctx, pf, precision):
     w = dense.full_spectrum(H)
     normH = max(abs(w[0]), abs(w[-1]))
     assert np.abs(single["E"] - res["E"][1]).max() <= 1e-10 * normH
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_mixes_j2_at_one_length(ctx, pf, precision):
+    """Two L = 12 members, one without and one with next-nearest couplings,
+    in one batch: each must get its own bond set in the batched filter (the
+    batch groups members by whether J2 is zero) and equal the dense answer."""
+    chains = [workloads.chain(12, 2.0, 71), workloads.chain(12, 2.0, 72, J2=1.0, Delta=0.55)]
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in chains]
+    nev = 8
+    res = ctx.solve_batch(models, nev, vectors=True, block_size=4, precision=precision)
+    assert res["status"] == [pf.OK, pf.OK]
+    for i, c in enumerate(chains):
+        H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+        w = dense.full_spectrum(H)
+        normH = max(abs(w[0]), abs(w[-1]))
+        Ed = w[dense.nearest_from_spectrum(w, res["info"][i]["sigma_energy"], nev)]
+        assert np.abs(res["E"][i] - Ed).max() <= 1e-10 * normH, i
+        V = res["V"][i]
+        assert np.linalg.norm(H @ V - V * res["E"][i], axis=0).max() <= 1e-8 * normH, i
+
+
+def test_batch_member_error_leaves_the_others(ctx, pf):
+    """A member whose target lies outside its own spectrum fails alone: its
+    status is POLFED_EINVAL and its outputs stay untouched, the others are
+    solved, and the call returns POLFED_NOT_CONVERGED (a warning)."""
+    good = workloads.chain(10, 2.0, 81)
+    narrow = workloads.chain(10, 0.05, 82, J1=0.05)   # spectrum within about +-0.3
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in (good, narrow, good)]
+    H = chain.hamiltonian_csr(good.L, good.J1, good.J2, good.Delta, good.h)
+    w = dense.full_spectrum(H)
+    normH = max(abs(w[0]), abs(w[-1]))
+    sigma = w[0] + 0.3 * (w[-1] - w[0])       # inside the first spectrum only
+    assert sigma < -1.0
+    res = ctx.solve_batch(models, 6, vectors=False, block_size=2, target_kind=1, target=sigma)
+    assert res["status"][1] == pf.EINVAL
+    assert np.isnan(res["E"][1]).all() and np.isnan(res["resid"][1]).all()  # untouched
+    assert res["status"][0] == pf.OK and res["status"][2] == pf.OK
+    assert res["rc"] == pf.NOT_CONVERGED
+    Ed = w[dense.nearest_from_spectrum(w, sigma, 6)]
+    for i in (0, 2):
+        assert np.abs(res["E"][i] - Ed).max() <= 1e-10 * normH

@@ -405,3 +405,56 @@ def test_hamiltonian_row_matches_csr():
         for st, v in row.items():
             dense_row[chain.rank([st], b)[0]] += v
         assert np.abs(dense_row - H.getrow(r).toarray().ravel()).max() < 1e-14
+
+
+def test_capped_window_definition_and_law():
+    """oracle.chebyshev.capped_window: the order fits the cap and one window
+    fewer does not (its definition, checked with choose_K), and the window
+    follows the paper's K ~ 1/N_win law (Supplement, "Benchmark": N_ev ->
+    a N_ev gives K -> K/a) to within 15%."""
+    L = 14
+    c = workloads.chain(L, 2.0, 5)
+    N = comb(L, L // 2)
+    E0w, E1w = -0.9 * L, 0.85 * L
+    Ebar = -(c.J1 + c.J2) * c.Delta * L / (4.0 * (L - 1))
+    G = chebyshev.dos_gamma(L, c.J1, c.J2, c.Delta, c.h)
+    nwin = 20
+    K0 = chebyshev.choose_K(nwin, 0.0, 0.17, N, Ebar, G, E0w, E1w)
+    for alpha in (2.0, 3.0):
+        cap = int(K0 / alpha)
+        w, K = chebyshev.capped_window(nwin, 0.0, 0.17, N, Ebar, G, E0w, E1w, cap)
+        assert K <= cap < chebyshev.choose_K(w - 1, 0.0, 0.17, N, Ebar, G, E0w, E1w)
+        assert abs(w / (alpha * nwin) - 1.0) < 0.15, (alpha, w)
+    # a cap above the order leaves the window alone
+    assert chebyshev.capped_window(nwin, 0.0, 0.17, N, Ebar, G, E0w, E1w, K0) == (nwin, K0)
+
+
+def test_sign_normalise_conventions():
+    """oracle.lanczos.sign_normalise: the entry of largest magnitude becomes
+    positive, and among entries of equal magnitude the lowest index decides
+    (the output convention of the eigenvectors).  Expected values written
+    out by hand."""
+    V = np.array([[0.5, -0.6, 0.3, 0.0],
+                  [-0.8, 0.6, -0.3, -0.0],
+                  [0.1, 0.2, 0.3, 0.0]])
+    out = lanczos.sign_normalise(V)
+    expect = np.array([[-0.5, 0.6, 0.3, 0.0],
+                       [0.8, -0.6, -0.3, 0.0],
+                       [-0.1, -0.2, 0.3, 0.0]])
+    assert np.array_equal(out, expect)
+    # a tie where the lowest index is the negative one flips the column
+    W = np.array([[-0.7], [0.7], [0.1]])
+    assert np.array_equal(lanczos.sign_normalise(W), np.array([[0.7], [-0.7], [-0.1]]))
+
+
+def test_extreme_eigenvalues_sparse_branch_vs_dense():
+    """oracle.lanczos.extreme_eigenvalues takes the ARPACK branch above 2000
+    rows (L = 14: 3,432); both extremes equal the dense eigvalsh ones to
+    1e-12 of ||H||."""
+    c = workloads.chain(14, 3.0, 77, J2=0.4, Delta=0.8)
+    H = chain.hamiltonian_csr(14, c.J1, c.J2, c.Delta, c.h)
+    assert H.shape[0] > 2000
+    lo, hi = lanczos.extreme_eigenvalues(H)
+    w = np.linalg.eigvalsh(H.toarray())
+    normH = max(abs(w[0]), abs(w[-1]))
+    assert abs(lo - w[0]) <= 1e-12 * normH and abs(hi - w[-1]) <= 1e-12 * normH
