@@ -104,35 +104,63 @@ __global__ __launch_bounds__(256) void k_gram(long long n, int p, int q, const d
   }
 }
 
-__global__ void k_gram_reduce(int p, int q, int nchunks, const double *part, double *C,
-                              long long ldc) {
-  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// C[i][j] = sum over chunks c of part[c][i][j]: one wavefront per output
+// element, lane l adding chunks l, l + 64, ... in order, then a fixed
+// butterfly over the lanes, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_gram_reduce(int p, int q, int nchunks,
+                                                     const double *part, double *C,
+                                                     long long ldc) {
+  const long long e = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (e >= (long long)p * q) return;
+  const size_t pq = (size_t)p * q;
   double s = 0.0;
-  for (int c = 0; c < nchunks; ++c) s += part[(size_t)c * p * q + e];
-  const int i = (int)(e / q), j = (int)(e % q);
-  C[(size_t)i * ldc + j] = s;
+  for (int c = lane; c < nchunks; c += 64) s += part[(size_t)c * pq + e];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+  if (lane == 0) {
+    const int i = (int)(e / q), j = (int)(e % q);
+    C[(size_t)i * ldc + j] = s;
+  }
+}
+
+// Row chunks of the Gram product for n rows and a p x q output: about four
+// workgroups per CU in all, at least 256 rows a chunk, and (cap > 0) no
+// more chunks than cap / (p q) partial tiles hold.
+long long gram_chunks(long long n, int p, int q, int num_cu, long long cap,
+                      long long &rows_per_chunk) {
+  const int tiles_m = (p + kGramTM - 1) / kGramTM;
+  const int tiles_n = (q + kGramTN - 1) / kGramTN;
+  long long want = std::max<long long>(1, (4LL * num_cu) / (tiles_m * tiles_n));
+  if (cap > 0) want = std::min<long long>(want, cap / ((long long)p * q));
+  want = std::max<long long>(want, 1);
+  rows_per_chunk = std::max<long long>(256, (n + want - 1) / want);
+  rows_per_chunk = ((rows_per_chunk + 15) / 16) * 16;
+  return std::max<long long>(1, (n + rows_per_chunk - 1) / rows_per_chunk);
+}
+
+void launch_gram_parts(hipStream_t st, long long n, int p, int q, const double *X,
+                       long long ldx, const double *Y, long long ldy, double *C, long long ldc,
+                       double *part, long long rows_per_chunk, long long nchunks) {
+  const int tiles_m = (p + kGramTM - 1) / kGramTM;
+  const int tiles_n = (q + kGramTN - 1) / kGramTN;
+  const long long nblk = nchunks * tiles_m * tiles_n;
+  k_gram<<<(unsigned)nblk, 256, 0, st>>>(n, p, q, X, ldx, Y, ldy, part, rows_per_chunk, tiles_m,
+                                         tiles_n);
+  check_launch("k_gram");
+  const long long tot = (long long)p * q;
+  k_gram_reduce<<<(unsigned)((tot + 3) / 4), 256, 0, st>>>(p, q, (int)nchunks, part, C, ldc);
+  check_launch("k_gram_reduce");
 }
 
 void launch_gram(hipStream_t st, long long n, int p, int q, const double *X, long long ldx,
                  const double *Y, long long ldy, double *C, long long ldc, DevBuf &partials,
                  int num_cu) {
   if (p <= 0 || q <= 0) return;
-  const int tiles_m = (p + kGramTM - 1) / kGramTM;
-  const int tiles_n = (q + kGramTN - 1) / kGramTN;
-  long long want = std::max<long long>(1, (4LL * num_cu) / (tiles_m * tiles_n));
-  long long rows_per_chunk = std::max<long long>(256, (n + want - 1) / want);
-  rows_per_chunk = ((rows_per_chunk + 15) / 16) * 16;
-  long long nchunks = std::max<long long>(1, (n + rows_per_chunk - 1) / rows_per_chunk);
+  long long rows_per_chunk = 0;
+  const long long nchunks = gram_chunks(n, p, q, num_cu, 0, rows_per_chunk);
   double *part = static_cast<double *>(partials.ensure(sizeof(double) * nchunks * p * q));
-  const long long nblk = nchunks * tiles_m * tiles_n;
-  k_gram<<<(unsigned)nblk, 256, 0, st>>>(n, p, q, X, ldx, Y, ldy, part, rows_per_chunk, tiles_m,
-                                         tiles_n);
-  check_launch("k_gram");
-  const long long tot = (long long)p * q;
-  k_gram_reduce<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(p, q, (int)nchunks, part, C,
-                                                               ldc);
-  check_launch("k_gram_reduce");
+  launch_gram_parts(st, n, p, q, X, ldx, Y, ldy, C, ldc, part, rows_per_chunk, nchunks);
 }
 
 // ---------------------------------------------------------------- update --

@@ -186,6 +186,15 @@ void launch_cast(hipStream_t st, long long n, int S, const Tin *in, long long ld
 void launch_gram(hipStream_t st, long long n, int p, int q, const double *X, long long ldx,
                  const double *Y, long long ldy, double *C, long long ldc, DevBuf &partials,
                  int num_cu);
+// The Gram product in its two launches, on partial tiles the caller
+// provides: gram_chunks picks the row chunks (about four workgroups per CU,
+// >= 256 rows each; cap > 0 limits them to cap / (p q) partial tiles) and
+// launch_gram_parts runs the MFMA kernel and the fixed-order chunk sum.
+long long gram_chunks(long long n, int p, int q, int num_cu, long long cap,
+                      long long &rows_per_chunk);
+void launch_gram_parts(hipStream_t st, long long n, int p, int q, const double *X,
+                       long long ldx, const double *Y, long long ldy, double *C, long long ldc,
+                       double *part, long long rows_per_chunk, long long nchunks);
 void launch_update(hipStream_t st, long long n, int p, int q, double alpha, const double *X,
                    long long ldx, const double *C, long long ldc, double beta, double *Y,
                    long long ldy);
