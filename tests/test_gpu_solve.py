@@ -155,8 +155,10 @@ def test_solve_invalid_arguments(ctx, pf):
 
 def test_solve_c2_vs_golden(ctx, pf):
     """L=18 J1-J2 (J2 = 1, Delta = 1), W = 2, N_ev = 50, s = 16, K from the
-    DOS, FP64: eigenvalues against the oracle's shift-invert values stored
-    in tests/golden/c2_j1j2_L18.json; residuals recomputed on the CPU."""
+    DOS, FP64: eigenvalues against the definition -- the 50 eigenvalues
+    nearest the target among the dense LAPACK eigenvalues of H in a window
+    around it, stored in tests/golden/c2_j1j2_L18.json by make_golden.py --
+    and residuals recomputed on the CPU."""
     g = json.load(open(os.path.join(GOLDEN, "c2_j1j2_L18.json")))
     wl = workloads.c2()
     c = wl.chains[0]
