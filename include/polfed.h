@@ -193,6 +193,20 @@ int polfed_apply_filter(polfed_ctx *ctx, const polfed_model *model, double E0,
 int polfed_gram(polfed_ctx *ctx, long long n, int p, int q, const double *X,
                 long long ldx, const double *Y, long long ldy, double *C,
                 long long ldc);
+/* polfed_gram for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same product, C (p x q, ldc) = X^T Y, with its partial tiles in a
+ * fixed 16 MiB device array of the library (one per GPU, held until the
+ * process ends) instead of the context's workspace; it calls no hipMalloc,
+ * hipFree or allocating routine.  The number of row chunks is limited so
+ * that their partial tiles fit the array, so results equal polfed_gram's to
+ * rounding (bitwise when the chunking is the same) and are deterministic.
+ * Needs p * q <= 2^21 (else POLFED_EINVAL with a message); n = 0 writes
+ * C = 0 (X and Y may then be NULL).  Calls that overlap in time on one GPU
+ * (two streams or two contexts) race on the array. */
+int polfed_gram_static(polfed_ctx *ctx, long long n, int p, int q, const double *X,
+                       long long ldx, const double *Y, long long ldy, double *C,
+                       long long ldc);
 int polfed_update(polfed_ctx *ctx, long long n, int p, int q, double alpha,
                   const double *X, long long ldx, const double *C,
                   long long ldc, double beta, double *Y, long long ldy);

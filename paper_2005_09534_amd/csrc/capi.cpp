@@ -142,6 +142,7 @@ int polfed_create(int device, polfed_ctx **out) {
     ctx->stream = ctx->own_stream;
     ctx->use_graphs = std::getenv("POLFED_NO_GRAPH") ? 0 : 1;
     upload_binomials(device);
+    init_gram_scratch(device);
   } catch (const Error &e) {
     delete ctx;
     t_create_error = e.what();
@@ -306,6 +307,17 @@ int polfed_gram(polfed_ctx *ctx, long long n, int p, int q, const double *X, lon
       return POLFED_OK;
     }
     launch_gram(ctx->stream, n, p, q, X, ldx, Y, ldy, C, ldc, ctx->buf("partials"), ctx->num_cu);
+    return POLFED_OK;
+  });
+}
+
+int polfed_gram_static(polfed_ctx *ctx, long long n, int p, int q, const double *X,
+                       long long ldx, const double *Y, long long ldy, double *C, long long ldc) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(n >= 0 && p >= 1 && q >= 1, "need n >= 0, p, q >= 1");
+    PF_REQUIRE(ldx >= p && ldy >= q && ldc >= q, "leading dimensions too small");
+    PF_REQUIRE(C && (n == 0 || (X && Y)), "NULL operand");
+    launch_gram_static(ctx->stream, ctx->device, n, p, q, X, ldx, Y, ldy, C, ldc, ctx->num_cu);
     return POLFED_OK;
   });
 }

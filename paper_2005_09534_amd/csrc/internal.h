@@ -195,6 +195,15 @@ long long gram_chunks(long long n, int p, int q, int num_cu, long long cap,
 void launch_gram_parts(hipStream_t st, long long n, int p, int q, const double *X,
                        long long ldx, const double *Y, long long ldy, double *C, long long ldc,
                        double *part, long long rows_per_chunk, long long nchunks);
+// noalloc.hip: the Gram product on the partial tiles of a fixed device
+// array of kGramScratchDoubles doubles (16 MiB), one copy per device;
+// init_gram_scratch(device) takes the array's device address once per
+// device, with the device current, before any call.
+constexpr size_t kGramScratchDoubles = (size_t)2 << 20;
+void init_gram_scratch(int device);
+void launch_gram_static(hipStream_t st, int device, long long n, int p, int q, const double *X,
+                        long long ldx, const double *Y, long long ldy, double *C,
+                        long long ldc, int num_cu);
 void launch_update(hipStream_t st, long long n, int p, int q, double alpha, const double *X,
                    long long ldx, const double *C, long long ldc, double beta, double *Y,
                    long long ldy);

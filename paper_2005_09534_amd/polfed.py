@@ -93,6 +93,8 @@ def _load():
                                         c_double, c_ll, c_int, c_int, c_void_p, c_void_p]),
         "polfed_gram": (c_int, [c_void_p, c_ll, c_int, c_int, c_void_p, c_ll, c_void_p, c_ll,
                                 c_void_p, c_ll]),
+        "polfed_gram_static": (c_int, [c_void_p, c_ll, c_int, c_int, c_void_p, c_ll, c_void_p,
+                                       c_ll, c_void_p, c_ll]),
         "polfed_update": (c_int, [c_void_p, c_ll, c_int, c_int, c_double, c_void_p, c_ll,
                                   c_void_p, c_ll, c_double, c_void_p, c_ll]),
         "polfed_sym_eig": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
@@ -274,6 +276,14 @@ class Context:
                                     _ptr(C), q), "gram")
         self.synchronize()
         return C
+
+    def gram_static(self, X, Y, out):
+        """polfed_gram_static into the preallocated tensor out (p x q)."""
+        n, p = X.shape
+        q = Y.shape[1]
+        self._check(LIB.polfed_gram_static(self.h, n, p, q, _ptr(X), X.stride(0), _ptr(Y),
+                                           Y.stride(0), _ptr(out), out.stride(0)), "gram_static")
+        return out
 
     def update(self, X, C, Y, alpha=1.0, beta=0.0):
         n, p = X.shape
