@@ -285,6 +285,29 @@ int polfed_set_filter_form(polfed_ctx *ctx, int form);
 int polfed_filter_stats(polfed_ctx *ctx, double *gpu_s, double *launches, double *bytes,
                         int reset);
 
+/* ---- observables of the eigenpairs (main text, "Entanglement entropy and
+ * level statistics") ----------------------------------------------------- */
+
+/* Entanglement entropy S_E = -sum_i alpha_i^2 ln(alpha_i^2) over the Schmidt
+ * coefficients alpha_i of each of nvec vectors (DEVICE, row-major
+ * polfed_dim(L) x nvec with leading dimension ldv >= nvec, unit norm, in the
+ * basis order of the header) for the bipartition of the ring at each of
+ * ncut cuts: cut x (host array cuts[c], 0 <= x < L) puts bits x .. x+L/2-1
+ * (mod L), i.e. sites x+1 .. x+L/2, in the first half.  S (HOST, nvec x
+ * ncut) receives S[j * ncut + c].  The coefficient matrix is block diagonal
+ * by the magnetisation of the first half; the blocks' Gram matrices are
+ * diagonalised on the device.  2 <= L <= 18 (blocks up to 128 x 128).
+ * Blocks the host until done. */
+int polfed_entanglement(polfed_ctx *ctx, int L, int nvec, const double *V, long long ldv,
+                        int ncut, const int *cuts, double *S);
+/* Mean gap ratio of n >= 3 levels E (host; any order): the average over
+ * consecutive sorted levels of r_i = min(g_i, g_{i+1}) / max(g_i, g_{i+1}),
+ * g_i = E_{i+1} - E_i. */
+int polfed_gap_ratio(const double *E, int n, double *rbar);
+/* S_RMT(L) = (L/2) ln 2 + (1/2 + ln(1/2))/2 - 1/2, the entropy of a chaotic
+ * chain in the zero-magnetisation sector, by which S_E is scaled. */
+double polfed_s_rmt(int L);
+
 /* Attainable device-memory bandwidth, for setting the step kernel's
  * achieved rate beside it: copies `bytes` bytes (a positive multiple of 16;
  * src and dst device pointers, 16-byte aligned, not overlapping) with a

@@ -17,6 +17,9 @@ reader can hold it against the paper:
 * ``lanczos``   -- spectral bounds, block Lanczos with full
   reorthogonalisation eqs. (Lan1)-(Lan2), Ritz extraction, Rayleigh-Ritz and
   residuals: the full POLFED solve.
+* ``observables`` -- entanglement entropy of eigenvectors over the half-ring
+  cuts and the mean gap ratio of eigenvalues (main text, "Entanglement
+  entropy and level statistics").
 * ``dense``     -- the definition of the answer: the N_ev eigenpairs of H
   nearest the target, by dense diagonalisation (or a library shift-invert
   eigensolver where dense is too large).
@@ -27,4 +30,4 @@ itself (brute force, a Kronecker-product construction, closed forms, free
 fermions, dense diagonalisation, invariants).
 """
 
-from . import chain, chebyshev, lanczos, dense  # noqa: F401
+from . import chain, chebyshev, lanczos, dense, observables  # noqa: F401

@@ -452,6 +452,29 @@ int polfed_filter_stats(polfed_ctx *ctx, double *gpu_s, double *launches, double
   });
 }
 
+int polfed_entanglement(polfed_ctx *ctx, int L, int nvec, const double *V, long long ldv,
+                        int ncut, const int *cuts, double *S) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(polfed_dim(L) > 0 && L >= 2 && L <= 18, "L must be even in [2, 18]");
+    PF_REQUIRE(nvec >= 1 && ldv >= nvec, "need nvec >= 1 and ldv >= nvec");
+    PF_REQUIRE(ncut >= 1 && cuts && V && S, "NULL argument or no cuts");
+    std::vector<int> cv(cuts, cuts + ncut);
+    for (int x : cv) PF_REQUIRE(x >= 0 && x < L, "cut offsets must be in [0, L)");
+    entanglement_entropy(ctx->stream, ctx->basis(L), nvec, V, ldv, cv, S, ctx->buf("ent"));
+    return POLFED_OK;
+  });
+}
+
+int polfed_gap_ratio(const double *E, int n, double *rbar) {
+  if (!E || !rbar || n < 3) return POLFED_EINVAL;
+  *rbar = mean_gap_ratio(E, n);
+  return POLFED_OK;
+}
+
+double polfed_s_rmt(int L) {
+  return 0.5 * L * std::log(2.0) + 0.5 * (0.5 + std::log(0.5)) - 0.5;
+}
+
 int polfed_stream_copy(polfed_ctx *ctx, const void *src, void *dst, long long bytes, int reps,
                        double *gbs) {
   return guarded(ctx, [&] {

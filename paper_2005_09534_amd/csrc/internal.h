@@ -267,6 +267,14 @@ void launch_lanczos_update(hipStream_t st, long long n, double *w, const double 
 void launch_lanczos_normalize(hipStream_t st, long long n, const double *w, double *vnext,
                               const double *part2, int nblk, double *beta);
 
+// observables.hip: S_E of nvec device vectors (row-major n x nvec, ld ldv)
+// for each cut (bit offset), into S_host[j * ncut + c] (L <= 18); and the
+// mean gap ratio of n >= 3 levels (host).
+void entanglement_entropy(hipStream_t st, const Basis &bs, int nvec, const double *V,
+                          long long ldv, const std::vector<int> &cuts, double *S_host,
+                          DevBuf &work);
+double mean_gap_ratio(const double *E, int n);
+
 // measure.hip: copy rate (read + write bytes per second / 1e9) of a plain
 // 16-byte-vector device copy of `bytes` bytes, repeated reps times.
 double stream_copy_gbs(hipStream_t st, const void *src, void *dst, long long bytes, int reps,

@@ -107,6 +107,10 @@ def _load():
         "polfed_set_filter_form": (c_int, [c_void_p, c_int]),
         "polfed_set_block_size": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
         "polfed_filter_stats": (c_int, [c_void_p, P_double, P_double, P_double, c_int]),
+        "polfed_entanglement": (c_int, [c_void_p, c_int, c_int, c_void_p, c_ll, c_int,
+                                        ctypes.POINTER(c_int), P_double]),
+        "polfed_gap_ratio": (c_int, [P_double, c_int, P_double]),
+        "polfed_s_rmt": (c_double, [c_int]),
         "polfed_stream_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_ll, c_int, P_double]),
         "polfed_solve": (c_int, [c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts), c_int,
                                  P_double, P_double, P_double, ctypes.POINTER(Info)]),
@@ -182,6 +186,20 @@ def window_order(model, E0w, E1w, sigma, nwin, max_order, p=0.17):
     if rc != OK:
         raise PolfedError(rc, "polfed_window_order")
     return nw.value, K.value
+
+
+def gap_ratio(E):
+    """Mean gap ratio of the levels E (polfed_gap_ratio)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    r = c_double()
+    rc = LIB.polfed_gap_ratio(E.ctypes.data_as(P_double), len(E), ctypes.byref(r))
+    if rc != OK:
+        raise PolfedError(rc, "polfed_gap_ratio")
+    return r.value
+
+
+def s_rmt(L):
+    return float(LIB.polfed_s_rmt(L))
 
 
 def _ptr(t):
@@ -339,6 +357,18 @@ class Context:
         self._check(LIB.polfed_filter_stats(self.h, ctypes.byref(g), ctypes.byref(l),
                                             ctypes.byref(b), int(reset)), "filter_stats")
         return dict(gpu_s=g.value, launches=l.value, bytes=b.value)
+
+    def entanglement(self, L, V, cuts=None):
+        """S_E of the columns of the device tensor V (n x nvec, FP64) for the
+        cuts (bit offsets; default 0 .. L/2-1): numpy array nvec x ncut."""
+        cuts = list(range(L // 2)) if cuts is None else list(cuts)
+        c = (c_int * len(cuts))(*cuts)
+        V = V.contiguous()
+        S = np.empty((V.shape[1], len(cuts)))
+        self._check(LIB.polfed_entanglement(self.h, L, V.shape[1], _ptr(V), V.stride(0),
+                                            len(cuts), c, S.ctypes.data_as(P_double)),
+                    "entanglement")
+        return S
 
     def stream_copy(self, src, dst, reps=10):
         """Copy rate (GB/s, read + write) of the library's plain copy kernel

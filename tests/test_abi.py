@@ -119,3 +119,13 @@ def test_one_hip_runtime_in_process():
             if "libamdhip64" in line:
                 paths.add(line.split()[-1])
     assert len(paths) == 1, paths
+
+
+def test_gap_ratio_and_s_rmt_match_oracle():
+    from oracle import observables
+    E = np.random.default_rng(4).standard_normal(200)
+    assert abs(pf.gap_ratio(E) - observables.mean_gap_ratio(E)) <= 1e-14
+    for L in (8, 14, 26):
+        assert abs(pf.s_rmt(L) - observables.s_rmt(L)) <= 1e-14
+    with pytest.raises(pf.PolfedError):
+        pf.gap_ratio([0.0, 1.0])

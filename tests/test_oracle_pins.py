@@ -458,3 +458,82 @@ def test_extreme_eigenvalues_sparse_branch_vs_dense():
     w = np.linalg.eigvalsh(H.toarray())
     normH = max(abs(w[0]), abs(w[-1]))
     assert abs(lo - w[0]) <= 1e-12 * normH and abs(hi - w[-1]) <= 1e-12 * normH
+
+
+# ---------------------------------------------------------------------------
+# observables: entanglement entropy and gap ratio (main text, "Entanglement
+# entropy and level statistics")
+# ---------------------------------------------------------------------------
+
+from oracle import observables  # noqa: E402
+
+
+def test_entropy_of_basis_states_is_zero():
+    L = 10
+    b = chain.basis(L)
+    for r in (0, 17, len(b) - 1):
+        v = np.zeros(len(b))
+        v[r] = 1.0
+        for x in range(L // 2):
+            assert observables.entanglement_entropy(v, L, x, b) == 0.0
+
+
+def test_entropy_of_singlets_across_the_cut():
+    """L = 8, a singlet on each of the bit pairs (0,1), (2,3), (4,5), (6,7):
+    the cut at bit x splits 0 (x even) or 2 (x odd) singlets, so S_E = 0 or
+    2 ln 2, and the cut average is ln 2 (closed form)."""
+    L = 8
+    b = chain.basis(L)
+    v = np.zeros(len(b))
+    for pattern in itertools.product((0, 1), repeat=4):   # which site of each pair is up
+        s, sign = 0, 1.0
+        for k, up_second in enumerate(pattern):
+            s |= 1 << (2 * k + up_second)
+            sign *= -1.0 if up_second else 1.0
+        v[chain.rank([s], b)[0]] = sign / 4.0
+    assert abs(np.linalg.norm(v) - 1.0) < 1e-15
+    for x in range(L // 2):
+        expect = 0.0 if x % 2 == 0 else 2.0 * np.log(2.0)
+        assert abs(observables.entanglement_entropy(v, L, x, b) - expect) < 1e-13
+    assert abs(observables.entanglement_entropy_cut_average(v, L, b) - np.log(2.0)) < 1e-13
+
+
+def test_entropy_svd_equals_reduced_density_matrix():
+    """Schmidt coefficients by SVD against the eigenvalues of the reduced
+    density matrix rho_A = psi psi^T (two library routes)."""
+    L = 10
+    b = chain.basis(L)
+    v = np.random.default_rng(3).standard_normal(len(b))
+    v /= np.linalg.norm(v)
+    for x in range(L // 2):
+        psi = observables.cut_matrix(v, L, x, b)
+        lam = np.linalg.eigvalsh(psi @ psi.T)
+        lam = lam[lam > 1e-300]
+        assert abs(observables.entanglement_entropy(v, L, x, b) + np.sum(lam * np.log(lam))) < 1e-12
+
+
+def test_random_state_entropy_near_s_rmt():
+    """A random state of the zero-magnetisation sector has the entropy of a
+    chaotic chain: within 0.01 of S_RMT(14) = 7 ln 2 + (1/2 + ln 1/2)/2 -
+    1/2 (dropping either correction term would miss by 0.1 or 0.5)."""
+    L = 14
+    b = chain.basis(L)
+    v = np.random.default_rng(14).standard_normal(len(b))
+    v /= np.linalg.norm(v)
+    s = observables.entanglement_entropy_cut_average(v, L, b)
+    assert abs(s - observables.s_rmt(L)) < 0.01
+    assert abs(observables.s_rmt(14) - (7 * np.log(2) + (0.5 + np.log(0.5)) / 2 - 0.5)) < 1e-15
+
+
+def test_gap_ratio_poisson_and_goe():
+    """Mean gap ratio of uncorrelated levels: 2 ln 2 - 1 = 0.3863; of a GOE
+    matrix (middle of its spectrum): 0.5307 (Atas et al., PRL 110, 084101
+    (2013)).  Sampling errors here are about 0.001 and 0.006."""
+    rng = np.random.default_rng(5)
+    E = np.cumsum(rng.exponential(size=100000))
+    assert abs(observables.mean_gap_ratio(E) - (2 * np.log(2) - 1)) < 0.01
+    A = rng.standard_normal((3000, 3000))
+    w = np.linalg.eigvalsh((A + A.T) / 2)
+    assert abs(observables.mean_gap_ratio(w[750:2250]) - 0.5307) < 0.02
+    r = observables.gap_ratios([0.0, 1.0, 3.0, 3.5])
+    assert np.allclose(r, [0.5, 0.25])
