@@ -19,8 +19,9 @@ filter's throughput on the same operator beside it, the attainable copy
 bandwidth, the FP64 Gram kernel at the solve's final shapes, and the
 oracle's throughput on the host cores.
 
-Other workloads (``--workload c1 | c2 | c3_fp32 | c3_fp64 | c4``) time
-complete solves (time to N_ev).
+Other workloads (``--workload c1 | c2 | c3_fp32 | c3_fp64 | c4`` and the
+paper's J1-J2 timing points ``j1j2_L20_nev100 | j1j2_L22_nev100 |
+j1j2_L22_nev200``) time complete solves (time to N_ev).
 """
 
 import argparse
@@ -201,7 +202,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5",
-                    choices=["c1", "c2", "c3_fp32", "c3_fp64", "c4", "c5", "c5_fp32"])
+                    choices=["c1", "c2", "c3_fp32", "c3_fp64", "c4", "c5", "c5_fp32",
+                             "j1j2_L20_nev100", "j1j2_L22_nev100", "j1j2_L22_nev200"])
     ap.add_argument("--K", type=int, default=64, help="fixed filter order of a c5 step")
     ap.add_argument("--blocks", type=int, default=2, help="Lanczos blocks of a c5 step")
     ap.add_argument("--shape", default="",
@@ -219,7 +221,10 @@ def main():
     big = args.workload.startswith("c5")
     wl = {"c1": workloads.c1, "c2": workloads.c2, "c3_fp64": lambda: workloads.c3("fp64"),
           "c3_fp32": lambda: workloads.c3("fp32"), "c4": workloads.c4,
-          "c5": workloads.c5, "c5_fp32": workloads.c5}[args.workload]()
+          "c5": workloads.c5, "c5_fp32": workloads.c5,
+          "j1j2_L20_nev100": lambda: workloads.j1j2_paper(20, 100),
+          "j1j2_L22_nev100": lambda: workloads.j1j2_paper(22, 100),
+          "j1j2_L22_nev200": lambda: workloads.j1j2_paper(22, 200)}[args.workload]()
     prec = 0 if args.workload == "c5" else (1 if wl.precision == "fp32" else 0)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
 

@@ -235,9 +235,14 @@ int polfed_bounds(polfed_ctx *ctx, const polfed_model *model, int steps,
  * whether the rank tables are staged in LDS (ignored for L > 28), whether
  * the streamed operands are loaded before the neighbour gathers
  * (early_loads != 0), and how neighbour ranks are found (rank_incremental
- * = 0: the two rank tables for every bond; != 0: from the row's own rank
- * by a binomial step for bonds that do not wrap round the chain, the
- * tables for the rest; the batched solve always uses the tables), and
+ * = 0: the two rank tables for every bond; 1: from the row's own rank by a
+ * binomial step for bonds that do not wrap round the chain, the tables for
+ * the rest; 2: from a stored pattern of the off-diagonal entries -- column
+ * indices only, the value J_l/2 implied, the paper's own matrix form
+ * (Supplement, "Technical details") -- built on the device at the first
+ * use for a chain length (4 bytes per entry, 8 per row), whose index
+ * reads the filter's byte count then includes; the batched solve always
+ * uses the tables), and
  * into how many column slices the block is split across the eight XCDs
  * (xcd_slices = 1, 2, 4 or 8; the workgroups of XCD x work on slice
  * x % xcd_slices over 8 / xcd_slices of the rows, so that each XCD's L2

@@ -5,7 +5,8 @@ Two choices are tuned, both through the C ABI of libpolfed:
 * the launch shape of the fused Chebyshev-step kernel (threads per group,
   16-byte loads per lane, persistent groups per CU, rank tables in LDS,
   streamed loads before or after the neighbour gathers, neighbour ranks from
-  the tables or incrementally, column slices across the XCDs) for a (chain
+  the tables, incrementally or from the stored pattern, column slices across
+  the XCDs) for a (chain
   length L, block width,
   precision): each candidate applies the filter for a few dozen steps to a
   random block of the chain and is timed with the library's HIP-event
@@ -35,9 +36,11 @@ import time
 LAUNCH = [(t, lpl, wpc) for t, lpl, wpc in
           itertools.product((256, 512, 1024), (1, 2, 4), (1, 2, 4, 8, 16))
           if wpc * t <= 2048]
+# (rank mode 2, the stored pattern, stages no tables: lds = 0 only)
 SHAPES = [(t, lpl, wpc, lds, early, ranki, xcd)
           for (t, lpl, wpc), lds, early, ranki, xcd in
-          itertools.product(LAUNCH, (1, 0), (0, 1), (0, 1), (1, 2, 4, 8))]
+          itertools.product(LAUNCH, (1, 0), (0, 1), (0, 1, 2), (1, 2, 4, 8))
+          if not (ranki == 2 and lds == 1)]
 
 
 def cache_path():

@@ -10,6 +10,9 @@
 // known index t = (L/2 - popcount(hi)) + u, so each half's term is a table
 // lookup and rank(s) = tabA[hi] + tabB[lo].  tabB[lo] is a rank among the
 // C(half, popcount(lo)) <= C(15, 7) low patterns and fits 16 bits.
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 
 namespace polfed {
@@ -105,6 +108,103 @@ void launch_rank(hipStream_t st, const Basis &b, long long n, const uint32_t *st
   k_rank<<<(unsigned)((n + th - 1) / th), th, 0, st>>>(states, ranks, n, b.tabA.as<int32_t>(),
                                                       b.tabB.as<uint16_t>(), b.L, b.half);
   check_launch("k_rank");
+}
+
+// ---- stored neighbour pattern (rank mode 2 of the step kernel) ----------
+
+__device__ __forceinline__ unsigned long long bond_mask(uint32_t s, int L, int has_j2) {
+  const uint32_t full = (L >= 32) ? 0xffffffffu : ((1u << L) - 1u);
+  const uint32_t rot1 = ((s >> 1) | (s << (L - 1))) & full;
+  unsigned long long mm = (unsigned long long)(s ^ rot1);
+  if (has_j2) {
+    const uint32_t rot2 = ((s >> 2) | (s << (L - 2))) & full;
+    mm |= (unsigned long long)(s ^ rot2) << 32;
+  }
+  return mm;
+}
+
+// counts of one block of 1024 rows: cnt[r] and the block total
+__global__ __launch_bounds__(1024) void k_pattern_count(const uint32_t *states, long long n,
+                                                         int L, int has_j2, long long *ptr,
+                                                         long long *bsum) {
+  __shared__ long long sh[1024];
+  const long long r = (long long)blockIdx.x * 1024 + threadIdx.x;
+  const long long c = (r < n) ? (long long)__popcll(bond_mask(states[r], L, has_j2)) : 0;
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {  // exclusive scan of the block, in order
+    long long run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const long long v = sh[i];
+      sh[i] = run;
+      run += v;
+    }
+    bsum[blockIdx.x] = run;
+  }
+  __syncthreads();
+  if (r < n) ptr[r] = sh[threadIdx.x];
+}
+
+__global__ void k_pattern_offsets(long long n, const long long *boff, long long *ptr,
+                                  long long nnz) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) ptr[r] += boff[r / 1024];
+  if (r == n) ptr[n] = nnz;
+}
+
+// col[ptr[r] ..]: the neighbours of row r in the step kernel's bond order
+__global__ void k_pattern_fill(const uint32_t *states, long long n, int L, int half, int has_j2,
+                               const int32_t *tabA, const uint16_t *tabB, const long long *ptr,
+                               int32_t *col) {
+  const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const uint32_t s = states[r];
+  unsigned long long mm = bond_mask(s, L, has_j2);
+  const uint32_t lomask = (1u << half) - 1u;
+  long long q = ptr[r];
+  while (mm) {
+    const int bit = __ffsll((long long)mm) - 1;
+    mm &= mm - 1ull;
+    const int l = (bit >= 32) ? 2 : 1;
+    const int i = bit & 31;
+    int j = i + l;
+    if (j >= L) j -= L;
+    const uint32_t f = s ^ ((1u << i) | (1u << j));
+    const int32_t rk = tabA[f >> half] + (int32_t)tabB[f & lomask];
+    col[q++] = (l == 2) ? (int32_t)((uint32_t)rk | 0x80000000u) : rk;
+  }
+}
+
+void build_pattern(hipStream_t st, const Basis &b, bool has_j2, Pattern &pat) {
+  const long long n = b.n;
+  const long long nb = (n + 1023) / 1024;
+  pat.n = n;
+  long long *ptr = static_cast<long long *>(pat.ptr.ensure(sizeof(long long) * (n + 1)));
+  DevBuf bsum;
+  long long *dsum = static_cast<long long *>(bsum.ensure(sizeof(long long) * nb));
+  k_pattern_count<<<(unsigned)nb, 1024, 0, st>>>(b.states.as<uint32_t>(), n, b.L, has_j2 ? 1 : 0,
+                                                 ptr, dsum);
+  check_launch("k_pattern_count");
+  std::vector<long long> hs(nb), ho(nb);
+  PF_HIP(hipMemcpyAsync(hs.data(), dsum, sizeof(long long) * nb, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
+  long long run = 0;
+  for (long long i = 0; i < nb; ++i) {
+    ho[i] = run;
+    run += hs[i];
+  }
+  PF_REQUIRE(run < (1LL << 40), "pattern too large");
+  pat.nnz = run;
+  PF_HIP(hipMemcpyAsync(dsum, ho.data(), sizeof(long long) * nb, hipMemcpyHostToDevice, st));
+  const int th = 256;
+  k_pattern_offsets<<<(unsigned)((n + 1 + th - 1) / th), th, 0, st>>>(n, dsum, ptr, run);
+  check_launch("k_pattern_offsets");
+  int32_t *col = static_cast<int32_t *>(pat.col.ensure(sizeof(int32_t) * std::max<long long>(1, run)));
+  k_pattern_fill<<<(unsigned)((n + th - 1) / th), th, 0, st>>>(
+      b.states.as<uint32_t>(), n, b.L, b.half, has_j2 ? 1 : 0, b.tabA.as<int32_t>(),
+      b.tabB.as<uint16_t>(), ptr, col);
+  check_launch("k_pattern_fill");
+  PF_HIP(hipStreamSynchronize(st));  // bsum is freed on return
 }
 
 struct DiagArgs {

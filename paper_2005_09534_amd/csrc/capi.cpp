@@ -76,6 +76,15 @@ static int guarded(polfed_ctx *ctx, F &&f) {
 
 using namespace polfed;
 
+const Pattern &polfed_ctx::pattern(int L, bool has_j2) {
+  auto &p = patterns[{L, has_j2 ? 1 : 0}];
+  if (!p) {
+    p.reset(new Pattern());
+    build_pattern(stream, basis(L), has_j2, *p);
+  }
+  return *p;
+}
+
 const Basis &polfed_ctx::basis(int L) {
   auto &p = bases[L];
   if (!p) {
@@ -156,6 +165,7 @@ int polfed_destroy(polfed_ctx *ctx) {
   if (!ctx) return POLFED_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  ctx->patterns.clear();
   ctx->bases.clear();
   ctx->bufs.clear();
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
@@ -371,6 +381,8 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
     PF_REQUIRE(threads == 256 || threads == 512 || threads == 1024,
                "threads must be 256, 512 or 1024");
     PF_REQUIRE(lpl == 1 || lpl == 2 || lpl == 4, "lpl must be 1, 2 or 4");
+    PF_REQUIRE(rank_incremental >= 0 && rank_incremental <= 2,
+               "rank mode must be 0 (tables), 1 (incremental) or 2 (stored pattern)");
     PF_REQUIRE(wg_per_cu >= 1 && wg_per_cu <= 32, "wg_per_cu must be in [1, 32]");
     PF_REQUIRE(xcd_slices == 1 || xcd_slices == 2 || xcd_slices == 4 || xcd_slices == 8,
                "xcd_slices must be 1, 2, 4 or 8");
@@ -380,7 +392,7 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
     sh.wg_per_cu = wg_per_cu;
     sh.lds_tables = lds_tables ? 1 : 0;
     sh.early_loads = early_loads ? 1 : 0;
-    sh.rank_incr = rank_incremental ? 1 : 0;
+    sh.rank_incr = rank_incremental;
     sh.xcd_slices = xcd_slices;
     ctx->shapes[std::make_tuple(L, nvec, precision ? 4 : 8)] = sh;
     return POLFED_OK;

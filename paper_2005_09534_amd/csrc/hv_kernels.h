@@ -24,13 +24,18 @@
 // own bit segment inside that XCD's L2.  The rank tables are staged in LDS
 // once per workgroup.
 //
-// Ranks of neighbours come from the two tables, or (RANKI) incrementally
+// Ranks of neighbours come from the two tables (rank mode RM = 0), or
+// (RM = 1) incrementally
 // from the row's own rank: in the colex rank sum_t C(p_t, t), moving the
 // particle with q particles below it from bit i to bit i+1 adds C(i, q)
 // (Pascal's rule on its one term); a hop from i to i+2 adds C(i, q) +
 // C(i+1, q + n_{i+1}) (two such moves, the second one over or past the
 // particle at i+1); the reverse moves subtract the same.  Bonds that wrap
-// round the chain renumber every particle and take the tables.
+// round the chain renumber every particle and take the tables.  RM = 2 reads
+// them from a stored pattern instead (the paper's own matrix form: column
+// indices only, the value J_l/2 implied by the bond range, which the top bit
+// of an index marks), built once per chain length in the same bond order, so
+// all three modes add the same terms in the same order.
 //
 // The forward three-term form t_{k+1} = 2 H~ t_k - t_{k-1} (the sum of
 // c_k T_k(H~) X accumulated term by term) is this kernel with W = t_{k-1}
@@ -105,7 +110,7 @@ struct Chunk {
 
 // One row of the fused step: out[r,:] for the lanes (col .. col+VEC) this
 // thread owns.  tA / tB are the rank tables (LDS or global).
-template <class T, int S, int LPL, bool EARLY, bool RANKI>
+template <class T, int S, int LPL, bool EARLY, int RM>
 __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int col,
                                          const int32_t *__restrict__ tA,
                                          const uint16_t *__restrict__ tB,
@@ -133,20 +138,29 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
   }
 
   if (a.V != nullptr) {
-    const uint32_t s = a.states[r];
+    const uint32_t s = (RM == 2) ? 0u : a.states[r];
     T self[VEC];
     load_row<T, VEC, LDV>(a.V + (size_t)r * a.ldv + col, self);
     const T dd = a.dscale * a.dt[r];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) acc[e] = dd * self[e];
 
-    // antiparallel bonds: bit i of s ^ rot_l(s) marks the pair (i, i+l)
-    const uint32_t rot1 = ((s >> 1) | (s << (L - 1))) & fullmask;
-    unsigned long long mm = (unsigned long long)(s ^ rot1);
-    if (a.has_j2) {
-      const uint32_t rot2 = ((s >> 2) | (s << (L - 2))) & fullmask;
-      mm |= (unsigned long long)(s ^ rot2) << 32;
+    // antiparallel bonds: bit i of s ^ rot_l(s) marks the pair (i, i+l);
+    // with the stored pattern, the row's index range [q, qe)
+    unsigned long long mm = 0ull;
+    long long q = 0, qe = 0;
+    if (RM == 2) {
+      q = a.csr_ptr[r];
+      qe = a.csr_ptr[r + 1];
+    } else {
+      const uint32_t rot1 = ((s >> 1) | (s << (L - 1))) & fullmask;
+      mm = (unsigned long long)(s ^ rot1);
+      if (a.has_j2) {
+        const uint32_t rot2 = ((s >> 2) | (s << (L - 2))) & fullmask;
+        mm |= (unsigned long long)(s ^ rot2) << 32;
+      }
     }
+    auto remaining = [&]() { return (RM == 2) ? (q < qe) : (mm != 0ull); };
     // Neighbours go in chunks of kChunk: the rank-table lookups of chunk c+1
     // are issued right after the gathers of chunk c, so each chunk costs one
     // round of memory latency (lookups and gathers overlap) rather than two.
@@ -157,14 +171,20 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
         idx[u] = -1;
-        if (mm) {
+        if (RM == 2) {
+          if (q < qe) {
+            const uint32_t e = (uint32_t)a.csr_col[q++];
+            idx[u] = (int32_t)(e & 0x7fffffffu);
+            if (e >> 31) two |= 1u << u;
+          }
+        } else if (mm) {
           const int bit = __ffsll((long long)mm) - 1;
           mm &= mm - 1ull;
           const int l = (bit >= 32) ? 2 : 1;
           const int i = bit & 31;
           int j = i + l;
           if (j >= L) j -= L;
-          if (RANKI && j > i) {
+          if (RM == 1 && j > i) {
             const int q = __popc(s & ((1u << i) - 1u));
             int d = tC[32 * i + q];
             if (l == 2) d += tC[32 * (i + 1) + q + (int)((s >> (i + 1)) & 1u)];
@@ -186,7 +206,7 @@ __device__ __forceinline__ void step_row(const StepArgs<T> &a, long long r, int 
       for (int u = 0; u < kChunk; ++u) {
         if (idx[u] >= 0) load_row<T, VEC, LDV>(a.V + (size_t)idx[u] * a.ldv + col, nb[u]);
       }
-      const bool more = (mm != 0ull);
+      const bool more = remaining();
       int32_t idx2[kChunk];
       uint32_t two2;
       fill(idx2, two2);  // no-op lookups when nothing is left
@@ -286,14 +306,14 @@ __device__ __forceinline__ void xcd_tiles(long long ntiles, int nslices, int &sl
   }
 }
 
-template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
+template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY, int RM>
 __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
   using C = StepCfg<T, S, LPL>;
   constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
   extern __shared__ int32_t s_tab[];
   const int32_t *tA, *tC;
   const uint16_t *tB;
-  stage_tables<LDS_TAB, RANKI>(a.tabA, a.tabB, a.binom, a.half, s_tab, tA, tB, tC);
+  stage_tables<LDS_TAB && RM != 2, RM == 1>(a.tabA, a.tabB, a.binom, a.half, s_tab, tA, tB, tC);
 
   const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
   const long long ntiles = (a.n + rows_per_iter - 1) / rows_per_iter;
@@ -315,7 +335,7 @@ __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
   for (long long t = t_begin; t < t_end; t += t_step) {
     const long long r = t * rows_per_iter + (long long)wave * RPW + slot;
     if (r >= a.n) continue;
-    step_row<T, S, LPL, EARLY, RANKI>(a, r, col, tA, tB, tC);
+    step_row<T, S, LPL, EARLY, RM>(a, r, col, tA, tB, tC);
   }
 }
 
@@ -381,24 +401,27 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
       a.w2 = (T)(0.5 * (double)it.w2 * it.Dinv);
       a.gamma = (T)(-it.Dinv);
     }
-    step_row<T, S, LPL, EARLY, false>(a, r, col, tA, tB, tC);
+    step_row<T, S, LPL, EARLY, 0>(a, r, col, tA, tB, tC);
   }
 }
 
-// Calls f.template operator()<LDS_TAB, MAXT, EARLY, RANKI>() for the
-// runtime choice (RANKI only where the launcher uses it).
-template <bool RANKI_USED, class F>
-static void dispatch_shape(bool lds, int threads, bool early, bool ranki, F &&f) {
+// Calls f.template operator()<LDS_TAB, MAXT, EARLY, RM>() for the runtime
+// choice (rank modes other than the tables only where the launcher uses
+// them; the stored pattern needs no tables in LDS).
+template <bool MODES_USED, class F>
+static void dispatch_shape(bool lds, int threads, bool early, int rank_mode, F &&f) {
   if (threads != 256 && threads != 512 && threads != 1024)
     throw Error(POLFED_EINVAL, "step kernel: threads must be 256, 512 or 1024");
   auto with_rank = [&](auto lds_c, auto thr_c, auto early_c) {
     constexpr bool LD = decltype(lds_c)::value;
     constexpr int TH = decltype(thr_c)::value;
     constexpr bool EA = decltype(early_c)::value;
-    if (RANKI_USED && ranki)
-      f.template operator()<LD, TH, EA, RANKI_USED>();
+    if (MODES_USED && rank_mode == 1)
+      f.template operator()<LD, TH, EA, MODES_USED ? 1 : 0>();
+    else if (MODES_USED && rank_mode == 2)
+      f.template operator()<false, TH, EA, MODES_USED ? 2 : 0>();
     else
-      f.template operator()<LD, TH, EA, false>();
+      f.template operator()<LD, TH, EA, 0>();
   };
   auto with_threads = [&](auto lds_c, auto early_c) {
     if (threads == 1024)
@@ -425,15 +448,15 @@ struct StepLaunch {
   long long nwg;
   int threads;
   size_t shm;
-  template <bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
+  template <bool LDS_TAB, int MAXT, bool EARLY, int RM>
   void operator()() const {
     // L = 28 tables (96 KB) exceed the default 64 KB of dynamic LDS per
     // group
     if (LDS_TAB && shm > 65536)
       PF_HIP(hipFuncSetAttribute(
-          reinterpret_cast<const void *>(k_step<T, S, LPL, LDS_TAB, MAXT, EARLY, RANKI>),
+          reinterpret_cast<const void *>(k_step<T, S, LPL, LDS_TAB, MAXT, EARLY, RM>),
           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    k_step<T, S, LPL, LDS_TAB, MAXT, EARLY, RANKI>
+    k_step<T, S, LPL, LDS_TAB, MAXT, EARLY, RM>
         <<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a);
   }
 };
@@ -447,7 +470,7 @@ struct BatchedLaunch {
   long long j, Kmax, nwg;
   int threads;
   size_t shm;
-  template <bool LDS_TAB, int MAXT, bool EARLY, bool RANKI>
+  template <bool LDS_TAB, int MAXT, bool EARLY, int RM>
   void operator()() const {
     if (LDS_TAB && shm > 65536)
       PF_HIP(hipFuncSetAttribute(
@@ -472,11 +495,13 @@ static void launch_step_s(hipStream_t st, const StepArgs<T> &a0, const StepShape
   // groups find no tile and exit
   nwg = ((nwg + 7) / 8) * 8;
   a.rows_per_wg = rows_per_iter;
-  const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
-  const bool ranki = shape.rank_incr != 0;
+  const int mode = shape.rank_incr;
+  if (mode == 2 && (a.csr_ptr == nullptr || a.csr_col == nullptr))
+    throw Error(POLFED_EINVAL, "step kernel: stored neighbour pattern not built");
+  const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL && mode != 2;
   const size_t shm =
-      lds ? (size_t)6 * ((size_t)1 << a.half) + (ranki ? sizeof(int32_t) * 32 * 32 : 0) : 0;
-  dispatch_shape<true>(lds, threads, shape.early_loads != 0, ranki,
+      lds ? (size_t)6 * ((size_t)1 << a.half) + (mode == 1 ? sizeof(int32_t) * 32 * 32 : 0) : 0;
+  dispatch_shape<true>(lds, threads, shape.early_loads != 0, mode,
                        StepLaunch<T, S, LPL>{st, a, nwg, threads, shm});
   check_launch("k_step");
 }
@@ -493,7 +518,7 @@ static void launch_batched_s(hipStream_t st, const StepArgs<T> &a, const BatchIt
   nwg = ((nwg + 7) / 8) * 8;
   const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
   const size_t shm = lds ? (size_t)6 * ((size_t)1 << a.half) : 0;
-  dispatch_shape<false>(lds, threads, shape.early_loads != 0, false,
+  dispatch_shape<false>(lds, threads, shape.early_loads != 0, 0,
                         BatchedLaunch<T, S, LPL>{st, a, items, B, j, Kmax, nwg, threads, shm});
   check_launch("k_step_batched");
 }

@@ -70,12 +70,22 @@ struct Basis {
   DevBuf binom;  // int32 C(n, k) at [32 n + k], n, k < 32
 };
 
+// Stored off-diagonal pattern of H (rank mode 2): per row, the column
+// indices of its neighbours in the kernel's bond order (J1 bonds by
+// ascending bit, then J2 bonds), the top bit of an index marking a J2 bond;
+// its values J_l/2 are implied.  One per (L, J2 != 0).
+struct Pattern {
+  long long n = 0, nnz = 0;
+  DevBuf ptr, col;  // int64 [n + 1], int32 [nnz]
+};
+
 // One chain (model + basis + diagonal in FP64).
 struct Chain {
   int L;
   double J1, J2, Delta;
   double h[32];
   const Basis *basis;
+  mutable const Pattern *pattern = nullptr;  // attached where a launch uses rank mode 2
   DevBuf diag;  // FP64 H[r][r]
 };
 
@@ -91,6 +101,7 @@ void build_basis(hipStream_t st, Basis &b, int L);
 void launch_rank(hipStream_t st, const Basis &b, long long n, const uint32_t *states,
                  int32_t *ranks);
 void launch_diag(hipStream_t st, const Chain &c, double *d);
+void build_pattern(hipStream_t st, const Basis &b, bool has_j2, Pattern &pat);
 template <class T>
 void launch_scaled_diag(hipStream_t st, long long n, const double *d, double a, double b, T *out);
 
@@ -136,6 +147,10 @@ struct StepArgs {
   // leading dimension is then that of the slice.
   int nslices;
   long long xss, vss, wss, oss, accss, srcss;
+  // stored neighbour pattern (rank mode 2): row r's neighbours are
+  // csr_col[csr_ptr[r] .. csr_ptr[r+1]), the top bit marking a J2 bond
+  const long long *csr_ptr;
+  const int32_t *csr_col;
 };
 
 // Launch shape of the step kernel (the autotuner's search space).
@@ -145,7 +160,8 @@ struct StepShape {
   int wg_per_cu = 8;     // persistent workgroups per CU
   int lds_tables = 1;    // stage rank tables in LDS
   int early_loads = 0;   // issue the streamed loads before the gathers
-  int rank_incr = 0;     // incremental ranks for bonds that do not wrap
+  int rank_incr = 0;     // neighbour ranks: 0 tables, 1 incremental for bonds
+                         // that do not wrap, 2 the stored pattern
   int xcd_slices = 1;    // column slices, one per XCD group (1, 2, 4, 8)
 };
 
@@ -307,6 +323,7 @@ struct polfed_ctx {
   hipStream_t stream = nullptr;
   std::string last_error;
   std::map<int, std::unique_ptr<polfed::Basis>> bases;  // per L
+  std::map<std::pair<int, int>, std::unique_ptr<polfed::Pattern>> patterns;  // per (L, J2 != 0)
   std::map<std::string, std::unique_ptr<polfed::DevBuf>> bufs;
   // HIP-event timing of the filter kernels (Chebyshev steps), accumulated
   // over a solve: GPU seconds between the first and last step of each
@@ -332,4 +349,5 @@ struct polfed_ctx {
     return *p;
   }
   const polfed::Basis &basis(int L);
+  const polfed::Pattern &pattern(int L, bool has_j2);
 };

@@ -63,17 +63,37 @@ static StepArgs<T> base_args(const Chain &c, const T *dt) {
   a.has_j2 = (c.J2 != 0.0) ? 1 : 0;
   a.binom = b.binom.as<int32_t>();
   a.nslices = 1;
+  if (c.pattern) {
+    a.csr_ptr = c.pattern->ptr.as<long long>();
+    a.csr_col = c.pattern->col.as<int32_t>();
+  }
   return a;
+}
+
+// The stored neighbour pattern of the chain, built on first use, where the
+// shape reads neighbours from it (rank mode 2).  Before any graph capture.
+static void attach_pattern(polfed_ctx *ctx, const Chain &c, const StepShape &shape) {
+  if (shape.rank_incr == 2 && !c.pattern) c.pattern = &ctx->pattern(c.L, c.J2 != 0.0);
 }
 
 // Algorithmic bytes of one step launch: each streamed block once (out, the
 // gathered V, W, X, and the accumulator's source and destination), plus the
-// state word and diagonal of every row when H~ is applied.
+// state word and diagonal of every row when H~ is applied -- or, when the
+// neighbours come from the stored pattern (rank mode 2), the diagonal, the
+// row pointers and every column index instead of the state word.
 template <class T>
-static double step_bytes(const StepArgs<T> &st, int S) {
+static double step_bytes(const StepArgs<T> &st, int S, int rank_mode = 0,
+                         const Pattern *pat = nullptr) {
   const int streams = (st.skip_out ? 0 : 1) + (st.V ? 1 : 0) + (st.W ? 1 : 0) +
                       (st.X ? 1 : 0) + (st.acc ? 2 : 0);
-  return (double)st.n * (S * (double)sizeof(T) * streams + (st.V ? 4.0 + sizeof(T) : 0.0));
+  double b = (double)st.n * (S * (double)sizeof(T) * streams);
+  if (st.V) {
+    if (rank_mode == 2 && pat)
+      b += (double)st.n * (8.0 + sizeof(T)) + 8.0 + 4.0 * (double)pat->nnz;
+    else
+      b += (double)st.n * (4.0 + sizeof(T));
+  }
+  return b;
 }
 
 static StepShape shape_for(const polfed_ctx *ctx, int L, int S, bool fp32) {
@@ -92,6 +112,7 @@ static void apply_op(polfed_ctx *ctx, const Chain &c, const T *dt, double wscale
   while (off < width) {
     int S = 64;
     while (S > width - off) S >>= 1;
+    attach_pattern(ctx, c, shape_for(ctx, c.L, S, fp32));
     StepArgs<T> a = base_args<T>(c, dt);
     a.V = V + off;
     a.ldv = ldv;
@@ -134,7 +155,7 @@ static double queue_filter_forward(hipStream_t stream, int num_cu, const StepSha
     st.ldx = ldx;
     st.alpha = (T)(coef[0] * Dinv);
     if (launch) launch_step<T>(stream, S, st, shape, num_cu);
-    return step_bytes(st, S);
+    return step_bytes(st, S, shape.rank_incr, c.pattern);
   }
   for (long long k = 1; k <= klast; ++k) {
     StepArgs<T> st = base_args<T>(c, dt);
@@ -177,7 +198,7 @@ static double queue_filter_forward(hipStream_t stream, int num_cu, const StepSha
       }
     }
     if (launch) launch_step<T>(stream, S, st, shape, num_cu);
-    moved += step_bytes(st, S);
+    moved += step_bytes(st, S, shape.rank_incr, c.pattern);
   }
   return moved;
 }
@@ -247,7 +268,7 @@ static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shap
     st.w2 = (T)(a * c.J2);
     st.gamma = T(-1);
     if (launch) launch_step<T>(stream, S, st, shape, num_cu);
-    moved += step_bytes(st, S);
+    moved += step_bytes(st, S, shape.rank_incr, c.pattern);
   }
   StepArgs<T> st = base_args<T>(c, dt);
   st.nslices = ns;
@@ -275,7 +296,7 @@ static double queue_filter(hipStream_t stream, int num_cu, const StepShape &shap
   st.w2 = (T)(0.5 * (a * c.J2) * Dinv);
   st.gamma = (T)(-Dinv);
   if (launch) launch_step<T>(stream, S, st, shape, num_cu);
-  moved += step_bytes(st, S);
+  moved += step_bytes(st, S, shape.rank_incr, c.pattern);
   return moved;
 }
 
@@ -293,6 +314,7 @@ static void run_filter(polfed_ctx *ctx, const Chain &c, const T *dt, double a, i
                        double *bytes, bool reused = true) {
   const long long n = c.basis->n;
   StepShape shape = shape_for(ctx, c.L, S, fp32);
+  attach_pattern(ctx, c, shape);
   if (!ctx->ev_start) {
     PF_HIP(hipEventCreate(&ctx->ev_start));
     PF_HIP(hipEventCreate(&ctx->ev_stop));
@@ -434,6 +456,7 @@ void run_bounds(polfed_ctx *ctx, const Chain &c, int steps, unsigned long long s
   launch_dot_partials(st, n, v[0], v[0], part2, nblk);
   launch_lanczos_normalize(st, n, v[0], v[0], part2, nblk, beta + steps);  // scratch beta slot
   launch_fill(st, beta, 1, 0.0);
+  attach_pattern(ctx, c, shape_for(ctx, c.L, 1, false));
   for (int k = 0; k < steps; ++k) {
     double *vk = v[k % 3];
     double *vprev = (k >= 1) ? v[(k + 2) % 3] : nullptr;

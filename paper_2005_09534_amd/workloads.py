@@ -85,6 +85,18 @@ def c5():
                     precision="fp32")
 
 
+def j1j2_paper(L, nev, precision="fp64", W=4.0, seed=7):
+    """The paper's J1-J2 benchmark model (J2 = 1, Delta = 0.55; main text,
+    "Benchmark models") at the sizes of its J1-J2 timing table (Supplement,
+    "Benchmark for disorder spin chains": L = 20 with N_ev = 100, 1000 and
+    L = 22 with N_ev = 100, 200, 1400, all at the middle of the spectrum).
+    The table does not state the disorder strength; W = 4 stands in for it.
+    Block size 16 (FP64) or 32 (FP32)."""
+    return Workload(f"j1j2_L{L}_D0.55_W{W:g}_nev{nev}_{precision}",
+                    [chain(L, W, seed, J2=1.0, Delta=0.55)], nev=nev,
+                    block=16 if precision == "fp64" else 32, precision=precision)
+
+
 def random_block(n, s, seed):
     """Seeded N(0,1) block (n x s), FP64, row-major: a test input."""
     return np.random.default_rng(seed).standard_normal((n, s))

@@ -22,8 +22,9 @@ def test_shape_candidates_are_valid():
     assert len(autotune.SHAPES) == len(set(autotune.SHAPES))
     for t, lpl, wpc, lds, early, ranki, xcd in autotune.SHAPES:
         assert t in (256, 512, 1024) and lpl in (1, 2, 4) and lds in (0, 1) and early in (0, 1)
-        assert ranki in (0, 1) and wpc >= 1 and xcd in (1, 2, 4, 8)
-    assert {sh[5] for sh in autotune.SHAPES} == {0, 1}
+        assert ranki in (0, 1, 2) and wpc >= 1 and xcd in (1, 2, 4, 8)
+        assert not (ranki == 2 and lds == 1)
+    assert {sh[5] for sh in autotune.SHAPES} == {0, 1, 2}
     assert {sh[6] for sh in autotune.SHAPES} == {1, 2, 4, 8}
 
 

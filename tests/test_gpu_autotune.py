@@ -42,8 +42,9 @@ def test_shapes_bitwise_identical(ctx, precision, width, J2):
     early = [sh for sh in unsliced if sh[4] == 1]
     ranki = [sh for sh in unsliced if sh[5] == 1]
     sliced = [sh for sh in autotune.SHAPES if sh[6] > 1 and sh[6] <= width]
-    assert early and ranki and (sliced or width == 1)
-    for sh in unsliced[::3] + early[::2] + ranki[::5] + sliced[::7]:
+    stored = [sh for sh in autotune.SHAPES if sh[5] == 2]
+    assert early and ranki and stored and (sliced or width == 1)
+    for sh in unsliced[::3] + early[::2] + ranki[::5] + sliced[::7] + stored[::5]:
         ctx.set_step_shape(c.L, width, precision, *sh)
         Y = ctx.apply_filter(m, E0w, E1w, 0.0, 40, X)
         torch.cuda.synchronize()

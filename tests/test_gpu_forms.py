@@ -185,8 +185,9 @@ def test_filter_form_rejects_unknown(ctx, pf):
                                              (22, 0.5, 32, torch.float32),
                                              (26, 0.0, 1, torch.float64)])
 def test_incremental_ranks_bitwise(ctx, pf, L, J2, nvec, dtype):
-    """H X with neighbour ranks from binomial steps equals H X with the rank
-    tables bit for bit, up to the full L = 26 chain (10,400,600 rows)."""
+    """H X with neighbour ranks from binomial steps, and with neighbours read
+    from the stored pattern, equals H X with the rank tables bit for bit, up
+    to the full L = 26 chain (10,400,600 rows)."""
     c = workloads.chain(L, 3.0, 40 + L, J2=J2)
     m = _model(pf, c)
     n = pf.dim(L)
@@ -199,11 +200,14 @@ def test_incremental_ranks_bitwise(ctx, pf, L, J2, nvec, dtype):
         Yt = ctx.apply_h(m, X)
         ctx.set_step_shape(L, nvec, prec, *saved[:5], 1)
         Yi = ctx.apply_h(m, X)
+        ctx.set_step_shape(L, nvec, prec, *saved[:5], 2)
+        Yp = ctx.apply_h(m, X)
         torch.cuda.synchronize()
         assert torch.equal(Yt, Yi)
+        assert torch.equal(Yt, Yp)
     finally:
         ctx.set_step_shape(L, nvec, prec, *saved)
-    del X, Yt, Yi
+    del X, Yt, Yi, Yp
     torch.cuda.empty_cache()
 
 
