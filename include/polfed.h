@@ -88,7 +88,18 @@ typedef struct {
                              gives K -> K/a at about the same filter work;
                              Supplement, "Benchmark for disorder spin
                              chains"), and info->nev_window reports it    */
+  int dos;                /* density of states of the order rule (K = 0):
+                             POLFED_DOS_GAUSS (default) the Gaussian of
+                             polfed_filter_order; POLFED_DOS_KPM the kernel
+                             polynomial estimate from dos_moments Chebyshev
+                             moments of H~ on dos_vectors random +-1
+                             vectors (polfed_dos_moments), for chains whose
+                             DOS is not Gaussian at the target            */
+  int dos_moments;        /* KPM moments M; 0 -> 256                       */
+  int dos_vectors;        /* KPM random vectors; 0 -> 4                    */
 } polfed_opts;
+
+enum polfed_dos { POLFED_DOS_GAUSS = 0, POLFED_DOS_KPM = 1 };
 
 /* Per-solve record (all times in seconds, wall clock on the host). */
 typedef struct {
@@ -161,6 +172,25 @@ int polfed_window_order(const polfed_model *model, double E0w, double E1w,
                         double sigma_tilde, int nwin, double p, long long max_order,
                         int *nwin_out, long long *K);
 
+/* Kernel polynomial method (the iterative DOS estimator the paper names
+ * for arbitrary sparse matrices, where K is chosen; main text "POLFED
+ * algorithm"): with Chebyshev moments mu[0..nmom-1] of H~ (from
+ * polfed_dos_moments) and Jackson damping
+ *   g_n = [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))]/(M+1),
+ * M = nmom, the number of states of an N-state sector in [x_lo, x_hi]
+ * (H~ units, clamped to [-1, 1]) is
+ *   N/pi [g_0 mu_0 (t_lo - t_hi) + 2 sum_{n>=1} g_n mu_n (sin n t_lo - sin n t_hi)/n],
+ * t = arccos x.  polfed_kpm_count writes it to *count. */
+int polfed_kpm_count(const double *mu, int nmom, long long N, double x_lo, double x_hi,
+                     double *count);
+/* The order rule of polfed_filter_order with the KPM count in place of the
+ * Gaussian: *K = max{K : count(main lobe {P_K >= p} around sigma_tilde) >=
+ * nwin}; with max_order > 0 and that K above it, the smallest window
+ * *nwin_out >= nwin whose order is at most max_order, as in
+ * polfed_window_order (else *nwin_out = nwin). */
+int polfed_kpm_order(const double *mu, int nmom, long long N, double sigma_tilde, int nwin,
+                     double p, long long max_order, int *nwin_out, long long *K);
+
 /* ---- stage calls (device pointers, async on the context stream) -------- */
 
 /* states[r] = the r-th Sz=0 state (uint32, length polfed_dim(L)). */
@@ -183,6 +213,20 @@ int polfed_apply_h(polfed_ctx *ctx, const polfed_model *model, int precision,
 int polfed_apply_filter(polfed_ctx *ctx, const polfed_model *model, double E0,
                         double E1, double sigma_tilde, long long K,
                         int precision, int nvec, const void *X, void *Y);
+
+/* Chebyshev moments of H~ = a H + b, a = 2/(E1w - E0w), b = -(E0w + E1w)/
+ * (E1w - E0w), for the kernel polynomial DOS (Silver et al.):
+ *   mu[j] = sum_r <r|T_j(H~)|r> / sum_r <r|r>,  j = 0 .. nmom-1,
+ * over the nvec columns r of R (device, n x nvec row-major, n =
+ * polfed_dim(L), read only), or, with R = NULL, of nvec vectors of +-1
+ * entries drawn from Philox4x32-10 keyed by seed.  With +-1 entries mu[j]
+ * estimates Tr T_j(H~) / n.  FP64; the moments come from floor(nmom/2)
+ * three-term steps by T_2k = 2 T_k^2 - 1 and T_2k+1 = 2 T_k+1 T_k - T_1;
+ * mu[0] = 1.  mu: host array of nmom.  1 <= nmom <= 2^20, nvec >= 1.
+ * Blocks the host until done; deterministic for fixed inputs. */
+int polfed_dos_moments(polfed_ctx *ctx, const polfed_model *model, double E0w, double E1w,
+                       int nmom, int nvec, const double *R, unsigned long long seed,
+                       double *mu);
 
 /* Tall-skinny FP64 products on the matrix cores (block Gram-Schmidt and
  * projection of eqs. (Lan1)-(Lan2) and the Ritz step).  All operands are

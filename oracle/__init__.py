@@ -20,6 +20,9 @@ reader can hold it against the paper:
 * ``observables`` -- entanglement entropy of eigenvectors over the half-ring
   cuts and the mean gap ratio of eigenvalues (main text, "Entanglement
   entropy and level statistics").
+* ``kpm``       -- the density of states by the kernel polynomial method
+  (Chebyshev moments from random vectors, Jackson damping, the count of
+  states in the filter's main lobe and the order rule built on it).
 * ``dense``     -- the definition of the answer: the N_ev eigenpairs of H
   nearest the target, by dense diagonalisation (or a library shift-invert
   eigensolver where dense is too large).
@@ -30,4 +33,4 @@ itself (brute force, a Kronecker-product construction, closed forms, free
 fermions, dense diagonalisation, invariants).
 """
 
-from . import chain, chebyshev, lanczos, dense, observables  # noqa: F401
+from . import chain, chebyshev, lanczos, dense, observables, kpm  # noqa: F401

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpolfed.so")
 
-SOURCES = ["basis.hip", "hv.hip", "hv_f32.hip", "dense.hip", "solver.hip", "measure.hip", "noalloc.hip", "observables.hip", "plan.cpp", "capi.cpp"]
+SOURCES = ["basis.hip", "hv.hip", "hv_f32.hip", "dense.hip", "solver.hip", "measure.hip", "noalloc.hip", "observables.hip", "dos.hip", "plan.cpp", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

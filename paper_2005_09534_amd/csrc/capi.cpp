@@ -119,6 +119,9 @@ void polfed_default_opts(polfed_opts *o) {
   o->bounds_steps = 200;
   o->seed = 12345;
   o->max_order = 0;
+  o->dos = POLFED_DOS_GAUSS;
+  o->dos_moments = 256;
+  o->dos_vectors = 4;
 }
 
 // Message of the last failed polfed_create on this host thread (there is no
@@ -230,6 +233,41 @@ int polfed_window_order(const polfed_model *m, double E0w, double E1w, double si
   *nwin_out = capped_window(n, Ebar, Gamma, E0w, E1w, sigma, (int)std::min<long long>(nwin, n), p,
                             max_order, K);
   return POLFED_OK;
+}
+
+int polfed_kpm_count(const double *mu, int nmom, long long N, double x_lo, double x_hi,
+                     double *count) {
+  if (!mu || !count || nmom < 1 || N < 0 || !(x_lo <= x_hi)) return POLFED_EINVAL;
+  *count = kpm_count(std::vector<double>(mu, mu + nmom), N, x_lo, x_hi);
+  return POLFED_OK;
+}
+
+int polfed_kpm_order(const double *mu, int nmom, long long N, double sigma, int nwin, double p,
+                     long long max_order, int *nwin_out, long long *K) {
+  if (!mu || !K || !nwin_out || nmom < 1 || N < 1 || nwin < 1 || !(std::fabs(sigma) < 1.0) ||
+      !(p > 0.0))
+    return POLFED_EINVAL;
+  const std::vector<double> m(mu, mu + nmom);
+  const int nw = (int)std::min<long long>(nwin, N);
+  *K = choose_order_kpm(m, N, sigma, nw, p);
+  *nwin_out = nw;
+  if (max_order > 0 && *K > max_order) *nwin_out = capped_window_kpm(m, N, sigma, nw, p, max_order, K);
+  return POLFED_OK;
+}
+
+int polfed_dos_moments(polfed_ctx *ctx, const polfed_model *m, double E0w, double E1w, int nmom,
+                       int nvec, const double *R, unsigned long long seed, double *mu) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(mu != nullptr, "mu is NULL");
+    PF_REQUIRE(E1w > E0w, "E1w must exceed E0w");
+    Chain c;
+    make_chain(ctx, m, c);
+    const double a = 2.0 / (E1w - E0w), b = -(E0w + E1w) / (E1w - E0w);
+    std::vector<double> out;
+    dos_moments(ctx, c, a, b, nmom, nvec, R, seed, out);
+    std::copy(out.begin(), out.end(), mu);
+    return POLFED_OK;
+  });
 }
 
 int polfed_basis(polfed_ctx *ctx, int L, uint32_t *states) {

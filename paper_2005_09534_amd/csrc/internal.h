@@ -306,6 +306,22 @@ long long choose_order(long long N, double Ebar, double Gamma, double E0w, doubl
                        double sigma, int nwin, double p, double *rho);
 int capped_window(long long N, double Ebar, double Gamma, double E0w, double E1w, double sigma,
                   int nwin, double p, long long K_cap, long long *K);
+// Kernel polynomial method (density of states from Chebyshev moments mu of
+// H~, Jackson damping): the number of states in [x_lo, x_hi], the density at
+// x, and the order rule and FP32 cap with that density in place of the
+// Gaussian.
+void jackson(int M, std::vector<double> &g);
+double kpm_count(const std::vector<double> &mu, long long N, double x_lo, double x_hi);
+double kpm_density(const std::vector<double> &mu, double x);
+long long choose_order_kpm(const std::vector<double> &mu, long long N, double sigma, int nwin,
+                           double p);
+int capped_window_kpm(const std::vector<double> &mu, long long N, double sigma, int nwin,
+                      double p, long long K_cap, long long *K);
+// dos.hip: Chebyshev moments mu_0 .. mu_{nmom-1} of H~ = aH + b from the nvec
+// columns of R (device, n x nvec row-major; NULL: +-1 entries from Philox
+// keyed by seed), mu_n = sum_r <r|T_n|r> / sum_r <r|r>, into mu (host).
+void dos_moments(polfed_ctx *ctx, const Chain &c, double a, double b, int nmom, int nvec,
+                 const double *R, unsigned long long seed, std::vector<double> &mu);
 // Extreme eigenvalues of the symmetric tridiagonal (alpha[k], beta[k] for
 // k=1..k-1 off-diagonal) and the last components of their unit
 // eigenvectors.

@@ -83,27 +83,29 @@ static double lobe_edge(double alpha, double t_out, long long K, double p) {
   return t_in;
 }
 
-static double n_in_window(long long K, double sigma, double p, long long N, double Ebar,
-                          double Gamma, double E0w, double E1w) {
+// Edges (x_lo, x_hi) of the main lobe {P_K >= p} around sigma.
+static void lobe(long long K, double sigma, double p, double &x_lo, double &x_hi) {
   const double alpha = std::acos(sigma);
   const double w = 2.0 * M_PI / (2.0 * (double)K + 1.0);
   const double th_r = lobe_edge(alpha, std::min(alpha + w, M_PI), K, p);
   const double th_l = lobe_edge(alpha, std::max(alpha - w, 0.0), K, p);
-  const double x_lo = std::cos(th_r), x_hi = std::cos(th_l);
+  x_lo = std::cos(th_r);
+  x_hi = std::cos(th_l);
+}
+
+static double n_in_window(long long K, double sigma, double p, long long N, double Ebar,
+                          double Gamma, double E0w, double E1w) {
+  double x_lo, x_hi;
+  lobe(K, sigma, p, x_lo, x_hi);
   const double Elo = 0.5 * (x_lo * (E1w - E0w) + (E1w + E0w));
   const double Ehi = 0.5 * (x_hi * (E1w - E0w) + (E1w + E0w));
   const double s = std::sqrt(2.0) * Gamma;
   return 0.5 * (double)N * (std::erf((Ehi - Ebar) / s) - std::erf((Elo - Ebar) / s));
 }
 
-long long choose_order(long long N, double Ebar, double Gamma, double E0w, double E1w,
-                       double sigma, int nwin, double p, double *rho) {
-  if (rho) {
-    const double E = 0.5 * (sigma * (E1w - E0w) + (E1w + E0w));
-    *rho = (double)N * (E1w - E0w) / (2.0 * std::sqrt(2.0 * M_PI) * Gamma) *
-           std::exp(-(E - Ebar) * (E - Ebar) / (2.0 * Gamma * Gamma));
-  }
-  auto f = [&](long long K) { return n_in_window(K, sigma, p, N, Ebar, Gamma, E0w, E1w); };
+// K = max{K : f(K) >= nwin} by doubling and bisection (f falls with K).
+template <class F>
+static long long order_rule(F &&f, int nwin) {
   const long long Kmax = 1LL << 26;
   if (f(1) < nwin) return 1;
   long long lo = 1, hi = 2;
@@ -122,17 +124,74 @@ long long choose_order(long long N, double Ebar, double Gamma, double E0w, doubl
   return lo;
 }
 
+long long choose_order(long long N, double Ebar, double Gamma, double E0w, double E1w,
+                       double sigma, int nwin, double p, double *rho) {
+  if (rho) {
+    const double E = 0.5 * (sigma * (E1w - E0w) + (E1w + E0w));
+    *rho = (double)N * (E1w - E0w) / (2.0 * std::sqrt(2.0 * M_PI) * Gamma) *
+           std::exp(-(E - Ebar) * (E - Ebar) / (2.0 * Gamma * Gamma));
+  }
+  return order_rule(
+      [&](long long K) { return n_in_window(K, sigma, p, N, Ebar, Gamma, E0w, E1w); }, nwin);
+}
+
+// ---- density of states by the kernel polynomial method --------------------
+//
+// With Chebyshev moments mu_n = Tr T_n(H~) / N of H~ (estimated from random
+// vectors, Silver et al.), the Jackson-damped density is
+//   rho(x) = [g_0 mu_0 + 2 sum_{n>=1} g_n mu_n T_n(x)] / (pi sqrt(1 - x^2)),
+//   g_n = [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))] / (M+1)
+// (Weisse et al., Rev. Mod. Phys. 78, 275 (2006)), and with x = cos(theta)
+// the number of states in [x_lo, x_hi] integrates in closed form:
+//   N / pi [g_0 mu_0 (t_lo - t_hi) + 2 sum g_n mu_n (sin n t_lo - sin n t_hi)/n].
+
+void jackson(int M, std::vector<double> &g) {
+  g.resize(M);
+  const double a = M_PI / (M + 1);
+  for (int n = 0; n < M; ++n)
+    g[n] = ((M - n + 1) * std::cos(a * n) + std::sin(a * n) / std::tan(a)) / (M + 1);
+}
+
+double kpm_count(const std::vector<double> &mu, long long N, double x_lo, double x_hi) {
+  const int M = (int)mu.size();
+  std::vector<double> g;
+  jackson(M, g);
+  const double tl = std::acos(std::max(-1.0, std::min(1.0, x_lo)));
+  const double th = std::acos(std::max(-1.0, std::min(1.0, x_hi)));
+  double s = g[0] * mu[0] * (tl - th);
+  for (int n = 1; n < M; ++n) s += 2.0 * g[n] * mu[n] * (std::sin(n * tl) - std::sin(n * th)) / n;
+  return (double)N * s / M_PI;
+}
+
+double kpm_density(const std::vector<double> &mu, double x) {
+  const int M = (int)mu.size();
+  std::vector<double> g;
+  jackson(M, g);
+  const double t = std::acos(std::max(-1.0, std::min(1.0, x)));
+  double s = g[0] * mu[0];
+  for (int n = 1; n < M; ++n) s += 2.0 * g[n] * mu[n] * std::cos(n * t);
+  return s / (M_PI * std::sqrt(std::max(1e-300, 1.0 - x * x)));
+}
+
+long long choose_order_kpm(const std::vector<double> &mu, long long N, double sigma, int nwin,
+                           double p) {
+  return order_rule(
+      [&](long long K) {
+        double x_lo, x_hi;
+        lobe(K, sigma, p, x_lo, x_hi);
+        return kpm_count(mu, N, x_lo, x_hi);
+      },
+      nwin);
+}
+
 // The smallest window count N >= nwin whose order K(N) = choose_order(N)
 // does not exceed K_cap (K_cap <= 0: no cap, N = nwin).  K(N) falls as N
 // grows (a wider window needs a shorter filter: N_ev -> alpha N_ev gives
 // K -> K / alpha at about the same total filter work; Supplement,
 // "Benchmark for disorder spin chains"), so N is found by doubling and
 // bisection; it is at most the sector size.  Writes that order to *K.
-int capped_window(long long N, double Ebar, double Gamma, double E0w, double E1w, double sigma,
-                  int nwin, double p, long long K_cap, long long *K) {
-  auto order = [&](long long w) {
-    return choose_order(N, Ebar, Gamma, E0w, E1w, sigma, (int)w, p, nullptr);
-  };
+template <class O>
+static int capped_window_by(O &&order, long long N, int nwin, long long K_cap, long long *K) {
   long long k = order(nwin);
   if (K_cap <= 0 || k <= K_cap || nwin >= N) {
     *K = k;
@@ -153,6 +212,19 @@ int capped_window(long long N, double Ebar, double Gamma, double E0w, double E1w
   }
   *K = order(hi);
   return (int)hi;
+}
+
+int capped_window(long long N, double Ebar, double Gamma, double E0w, double E1w, double sigma,
+                  int nwin, double p, long long K_cap, long long *K) {
+  return capped_window_by(
+      [&](long long w) { return choose_order(N, Ebar, Gamma, E0w, E1w, sigma, (int)w, p, nullptr); },
+      N, nwin, K_cap, K);
+}
+
+int capped_window_kpm(const std::vector<double> &mu, long long N, double sigma, int nwin,
+                      double p, long long K_cap, long long *K) {
+  return capped_window_by(
+      [&](long long w) { return choose_order_kpm(mu, N, sigma, (int)w, p); }, N, nwin, K_cap, K);
 }
 
 // ---- tridiagonal extremes (bounds Lanczos) --------------------------------

@@ -513,6 +513,10 @@ static polfed_opts resolve_opts(const polfed_opts *in) {
   if (o.tol <= 0.0) o.tol = 1e-10;
   if (o.eta <= 0.0) o.eta = 1e-3;
   if (o.bounds_steps <= 0) o.bounds_steps = 200;
+  if (o.dos_moments <= 0) o.dos_moments = 256;
+  if (o.dos_vectors <= 0) o.dos_vectors = 4;
+  PF_REQUIRE(o.dos == POLFED_DOS_GAUSS || o.dos == POLFED_DOS_KPM, "dos must be 0 or 1");
+  PF_REQUIRE(o.dos_moments <= (1 << 20), "dos_moments must be at most 2^20");
   PF_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
   PF_REQUIRE(o.target_kind == 0 || o.target_kind == 1, "target_kind must be 0 or 1");
   if (o.target_kind == 0) PF_REQUIRE(o.target > 0.0 && o.target < 1.0, "eps target must be in (0,1)");
@@ -634,18 +638,25 @@ void Realization<T>::setup(polfed_ctx *ctx_, const polfed_model *model, const po
   nwin = (int)std::min<long long>((long long)std::ceil(o.window_factor * nev), n);
   K = o.K;
   if (K <= 0) {
-    double rho = 0.0;
-    const double Gamma = dos_gamma(c.L, c.J1, c.J2, c.Delta, c.h);
-    const double Ebar = trace_mean(c.L, c.J1, c.J2, c.Delta);
-    K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, &rho);
     // FP32 filter: its rounding error grows like eps32 sqrt(K); beyond the
     // cap the window is widened until K fits (the wider window then counts
     // as one wider than the default for the stop rule)
     const long long cap = (o.max_order > 0) ? o.max_order : kFp32MaxOrder;
-    if (fp32 && K > cap) {
-      nwin = capped_window(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, cap, &K);
-      o.window_factor = std::max(o.window_factor, (double)nwin / nev);
+    const int nwin0 = nwin;
+    if (o.dos == POLFED_DOS_KPM) {
+      // kernel polynomial DOS from Chebyshev moments of this H~
+      std::vector<double> mu;
+      dos_moments(ctx, c, a, b, o.dos_moments, o.dos_vectors, nullptr, o.seed ^ 0xd05d05ull, mu);
+      K = choose_order_kpm(mu, n, sigma, nwin, o.p);
+      if (fp32 && K > cap) nwin = capped_window_kpm(mu, n, sigma, nwin, o.p, cap, &K);
+    } else {
+      double rho = 0.0;
+      const double Gamma = dos_gamma(c.L, c.J1, c.J2, c.Delta, c.h);
+      const double Ebar = trace_mean(c.L, c.J1, c.J2, c.Delta);
+      K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, &rho);
+      if (fp32 && K > cap) nwin = capped_window(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, cap, &K);
     }
+    if (nwin != nwin0) o.window_factor = std::max(o.window_factor, (double)nwin / nev);
   }
   cheb_coeffs(sigma, K, coef, D);
   // column cap: 8 N_win + 8 s in whole blocks, at most n, and the Lanczos

@@ -35,7 +35,8 @@ class Opts(ctypes.Structure):
                 ("K", c_ll), ("p", c_double), ("precision", c_int),
                 ("window_factor", c_double), ("max_cols", c_int), ("tol", c_double),
                 ("eta", c_double), ("bounds_steps", c_int), ("seed", c_ull),
-                ("max_order", c_ll)]
+                ("max_order", c_ll), ("dos", c_int), ("dos_moments", c_int),
+                ("dos_vectors", c_int)]
 
 
 class Info(ctypes.Structure):
@@ -110,6 +111,11 @@ def _load():
         "polfed_entanglement": (c_int, [c_void_p, c_int, c_int, c_void_p, c_ll, c_int,
                                         ctypes.POINTER(c_int), P_double]),
         "polfed_gap_ratio": (c_int, [P_double, c_int, P_double]),
+        "polfed_kpm_count": (c_int, [P_double, c_int, c_ll, c_double, c_double, P_double]),
+        "polfed_kpm_order": (c_int, [P_double, c_int, c_ll, c_double, c_int, c_double, c_ll,
+                                     ctypes.POINTER(c_int), ctypes.POINTER(c_ll)]),
+        "polfed_dos_moments": (c_int, [c_void_p, ctypes.POINTER(Model), c_double, c_double,
+                                       c_int, c_int, c_void_p, c_ull, P_double]),
         "polfed_s_rmt": (c_double, [c_int]),
         "polfed_stream_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_ll, c_int, P_double]),
         "polfed_solve": (c_int, [c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts), c_int,
@@ -185,6 +191,30 @@ def window_order(model, E0w, E1w, sigma, nwin, max_order, p=0.17):
                                  ctypes.byref(nw), ctypes.byref(K))
     if rc != OK:
         raise PolfedError(rc, "polfed_window_order")
+    return nw.value, K.value
+
+
+def kpm_count(mu, N, x_lo, x_hi):
+    """States of an N-state sector in [x_lo, x_hi] of H~ from the Chebyshev
+    moments mu (polfed_kpm_count)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    out = c_double()
+    rc = LIB.polfed_kpm_count(mu.ctypes.data_as(P_double), len(mu), N, x_lo, x_hi,
+                              ctypes.byref(out))
+    if rc != OK:
+        raise PolfedError(rc, "polfed_kpm_count")
+    return out.value
+
+
+def kpm_order(mu, N, sigma, nwin, p=0.17, max_order=0):
+    """(window count, K) of the order rule with the KPM density (polfed_kpm_order)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    nw = c_int()
+    K = c_ll()
+    rc = LIB.polfed_kpm_order(mu.ctypes.data_as(P_double), len(mu), N, sigma, nwin, p, max_order,
+                              ctypes.byref(nw), ctypes.byref(K))
+    if rc != OK:
+        raise PolfedError(rc, "polfed_kpm_order")
     return nw.value, K.value
 
 
@@ -369,6 +399,19 @@ class Context:
                                             len(cuts), c, S.ctypes.data_as(P_double)),
                     "entanglement")
         return S
+
+    def dos_moments(self, model, E0w, E1w, nmom, R=None, nvec=4, seed=1):
+        """Chebyshev moments of H~ (polfed_dos_moments): from the columns of
+        the device tensor R (n x nvec, FP64), or from nvec Philox +-1
+        vectors keyed by seed when R is None.  numpy array of nmom."""
+        mu = np.empty(nmom)
+        if R is not None:
+            R = R.contiguous()
+            nvec = R.shape[1]
+        self._check(LIB.polfed_dos_moments(self.h, ctypes.byref(model), E0w, E1w, nmom, nvec,
+                                           None if R is None else _ptr(R), seed,
+                                           mu.ctypes.data_as(P_double)), "dos_moments")
+        return mu
 
     def stream_copy(self, src, dst, reps=10):
         """Copy rate (GB/s, read + write) of the library's plain copy kernel

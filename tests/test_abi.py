@@ -33,6 +33,7 @@ def test_dim_invalid(L):
 def test_default_opts():
     o = pf.default_opts()
     assert o.target == 0.5 and o.p == 0.17 and o.window_factor == 1.5 and o.tol == 1e-10
+    assert o.dos == 0 and o.dos_moments == 256 and o.dos_vectors == 4
 
 
 @pytest.mark.parametrize("sigma", [0.0, 0.37, -0.8])
@@ -129,3 +130,47 @@ def test_gap_ratio_and_s_rmt_match_oracle():
         assert abs(pf.s_rmt(L) - observables.s_rmt(L)) <= 1e-14
     with pytest.raises(pf.PolfedError):
         pf.gap_ratio([0.0, 1.0])
+
+
+def _exact_moments(L, W, seed, M, J2=0.0, Delta=1.0):
+    from oracle import chain, dense, kpm, lanczos
+    c = workloads.chain(L, W, seed, J2=J2, Delta=Delta)
+    H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+    w = dense.full_spectrum(H)
+    E0w, E1w = lanczos.widened_bounds(w[0], w[-1], 1e-3)
+    a, b = chebyshev.rescale_coeffs(E0w, E1w)
+    return kpm.moments_exact(w, a, b, M), w, a, b
+
+
+@pytest.mark.parametrize("M", [1, 16, 256])
+def test_kpm_count_matches_oracle(M):
+    """The library's closed-form KPM count against the oracle's quadrature
+    of the Jackson-damped density, on an L = 12 spectrum's moments."""
+    from oracle import kpm
+    mu, w, a, b = _exact_moments(12, 3.0, 21, M)
+    N = len(w)
+    for lo, hi in [(-1.0, 1.0), (-0.31, 0.07), (0.5, 0.5005), (-2.0, -0.9)]:
+        got = pf.kpm_count(mu, N, lo, hi)
+        ref = kpm.count(mu, N, lo, hi)
+        assert abs(got - ref) <= 1e-9 * max(1.0, abs(ref)), (lo, hi, got, ref)
+    with pytest.raises(pf.PolfedError):
+        pf.kpm_count(mu, N, 0.2, 0.1)
+
+
+@pytest.mark.parametrize("L,W,J2,Delta,eps", [(12, 8.0, 0.0, 1.0, 0.3), (14, 0.5, 1.0, 0.55, 0.85),
+                                             (14, 5.0, 0.0, 1.0, 0.5)])
+def test_kpm_order_matches_oracle(L, W, J2, Delta, eps):
+    """polfed_kpm_order (doubling and bisection with the closed-form count)
+    is the oracle's KPM order rule, integer-exact; under a cap the window is
+    the smallest whose order fits."""
+    from oracle import kpm
+    mu, w, a, b = _exact_moments(L, W, 11 if J2 == 0.0 else 12, 256, J2=J2, Delta=Delta)
+    N = len(w)
+    sig_t = a * (w[0] + eps * (w[-1] - w[0])) + b
+    nw, K = pf.kpm_order(mu, N, sig_t, 30)
+    assert nw == 30 and K == kpm.choose_K(30, sig_t, 0.17, mu, N)
+    cap = max(2, K // 3)
+    nw2, K2 = pf.kpm_order(mu, N, sig_t, 30, max_order=cap)
+    assert nw2 > 30 and K2 <= cap
+    assert K2 == kpm.choose_K(nw2, sig_t, 0.17, mu, N)
+    assert kpm.choose_K(nw2 - 1, sig_t, 0.17, mu, N) > cap

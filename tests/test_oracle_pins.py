@@ -537,3 +537,117 @@ def test_gap_ratio_poisson_and_goe():
     assert abs(observables.mean_gap_ratio(w[750:2250]) - 0.5307) < 0.02
     r = observables.gap_ratios([0.0, 1.0, 3.0, 3.5])
     assert np.allclose(r, [0.5, 0.25])
+
+
+# ---------------------------------------------------------------------------
+# kernel polynomial density of states: trace identity, Jackson's kernel,
+# closed-form measures, brute-force order rule
+# ---------------------------------------------------------------------------
+
+from oracle import kpm  # noqa: E402
+
+
+def _chain_spectrum(L, W, seed, J2=0.0, Delta=1.0):
+    c = workloads.chain(L, W, seed, J2=J2, Delta=Delta)
+    H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
+    w = dense.full_spectrum(H)
+    E0w, E1w = lanczos.widened_bounds(w[0], w[-1], 1e-3)
+    a, b = chebyshev.rescale_coeffs(E0w, E1w)
+    return H, w, a, b
+
+
+@pytest.mark.parametrize("L,J2", [(8, 0.0), (10, 1.0)])
+def test_kpm_stochastic_moments_over_a_basis_are_the_trace(L, J2):
+    """Summed over the columns of any orthonormal basis (the unit vectors, or
+    a random orthogonal matrix), sum_r <r|T_n(H~)|r> = Tr T_n(H~) = sum_i
+    T_n(x_i) over the eigenvalues: the recurrence route against dense
+    diagonalisation."""
+    H, w, a, b = _chain_spectrum(L, 3.0, 5, J2=J2)
+    N = H.shape[0]
+    M = 41
+    ref = kpm.moments_exact(w, a, b, M)
+    assert ref[0] == 1.0
+    assert np.abs(kpm.moments_stochastic(H, a, b, np.eye(N), M) - ref).max() < 1e-12
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((N, N)))
+    assert np.abs(kpm.moments_stochastic(H.toarray(), a, b, Q, M) - ref).max() < 1e-12
+    # a single eigenvector gives the moments of one level: T_n(x_i)
+    ev = np.linalg.eigh(H.toarray())[1][:, 7]
+    x7 = a * w[7] + b
+    mu1 = kpm.moments_stochastic(H, a, b, 3.0 * ev, M)
+    assert np.abs(mu1 - np.cos(np.arange(M) * np.arccos(x7))).max() < 1e-12
+
+
+@pytest.mark.parametrize("M", [1, 2, 5, 16, 101, 256])
+def test_jackson_kernel_closed_values_and_autocorrelation(M):
+    """g_0 = 1, g_1 = cos(pi/(M+1)) (so a single level at x_0 keeps its mean
+    at g_1 x_0), and g_n equals the normalised autocorrelation
+    sum_v a_v a_{v+n} / sum_v a_v^2 of a_v = sin(pi (v+1)/(M+1)) -- the form
+    that makes the damped density non-negative."""
+    g = kpm.jackson(M)
+    assert abs(g[0] - 1.0) < 1e-14
+    if M > 1:
+        assert abs(g[1] - np.cos(pi / (M + 1))) < 1e-14
+    av = np.sin(pi * (np.arange(M) + 1) / (M + 1))
+    auto = np.array([np.dot(av[:M - n], av[n:]) for n in range(M)]) / np.dot(av, av)
+    assert np.abs(g - auto).max() < 1e-13
+
+
+@pytest.mark.parametrize("M", [1, 8, 64])
+def test_kpm_count_of_the_chebyshev_measure(M):
+    """mu = (1, 0, 0, ...) is the measure 1/(pi sqrt(1 - x^2)): the count in
+    [x_lo, x_hi] is N (arccos x_lo - arccos x_hi)/pi for any M."""
+    mu = np.zeros(M)
+    mu[0] = 1.0
+    for x_lo, x_hi in [(-1.0, 1.0), (-0.3, 0.2), (0.9, 0.95), (-1.0, -0.99)]:
+        ref = 1000 * (np.arccos(x_lo) - np.arccos(x_hi)) / pi
+        assert abs(kpm.count(mu, 1000, x_lo, x_hi) - ref) < 1e-9
+
+
+@pytest.mark.parametrize("x0", [0.0, 0.37, -0.8])
+def test_kpm_single_level_weight_and_mean(x0):
+    """A single level at x_0 (mu_n = T_n(x_0)): total weight 1 (count N over
+    [-1, 1]) and mean position g_1 x_0, by quadrature of the density."""
+    M = 64
+    mu = np.cos(np.arange(M) * np.arccos(x0))
+    assert abs(kpm.count(mu, 50, -1.0, 1.0) - 50.0) < 1e-9
+    f = lambda t: float(kpm.density(mu, np.cos(t))[0] * np.cos(t) * np.sin(t))
+    mean, _ = scipy.integrate.quad(f, 1e-9, pi - 1e-9, limit=500)
+    assert abs(mean - np.cos(pi / (M + 1)) * x0) < 1e-6
+
+
+def test_kpm_density_of_a_spectrum_nonnegative_and_counts():
+    """Exact moments of an L = 12 spectrum: the Jackson-damped density is
+    non-negative, integrates to N, and counts the eigenvalues of an interval
+    to within the kernel's resolution (pi/M) at the interval's ends."""
+    H, w, a, b = _chain_spectrum(12, 2.0, 9)
+    N = H.shape[0]
+    x = a * w + b
+    for M in (64, 512):
+        mu = kpm.moments_exact(w, a, b, M)
+        grid = np.linspace(-0.999, 0.999, 2001)
+        assert kpm.density(mu, grid).min() > -1e-10
+        assert abs(kpm.count(mu, N, -1.0, 1.0) - N) < 1e-7
+        for lo, hi in [(-0.2, 0.1), (0.3, 0.5)]:
+            res = 3.0 * pi / M  # a few kernel widths
+            inner = int(((x > lo + res) & (x < hi - res)).sum())
+            outer = int(((x > lo - res) & (x < hi + res)).sum())
+            cnt = kpm.count(mu, N, lo, hi)
+            assert inner - 1 <= cnt <= outer + 1, (M, lo, hi, inner, cnt, outer)
+
+
+def test_kpm_choose_K_against_a_scan():
+    """The KPM order rule is max{K : n_P(K) >= nwin}: against a linear scan
+    of n_P over K (Chebyshev measure, N = 2000, sigma~ = 0.3), and on a real
+    spectrum's moments the lobe of the chosen K holds about nwin of its
+    eigenvalues."""
+    mu = np.zeros(16)
+    mu[0] = 1.0
+    K = kpm.choose_K(20, 0.3, 0.17, mu, 2000)
+    f = [kpm.n_P(k, 0.3, 0.17, mu, 2000) for k in range(1, 200)]
+    assert K == max(k for k, v in zip(range(1, 200), f) if v >= 20)
+    H, w, a, b = _chain_spectrum(14, 1.0, 11)
+    sig_t = a * (w[0] + 0.2 * (w[-1] - w[0])) + b
+    mu = kpm.moments_exact(w, a, b, 256)
+    K = kpm.choose_K(30, sig_t, 0.17, mu, H.shape[0])
+    inside = int((chebyshev.P_of_x(a * w + b, sig_t, K) >= 0.17).sum())
+    assert 27 <= inside <= 33
