@@ -254,7 +254,7 @@ def main():
             form, secs = autotune.tune_form(ctx, c, wl.block, prec)
             form_times = {"chosen": "forward" if form == pf.FORM_FORWARD else "clenshaw",
                           "clenshaw_s": secs[pf.FORM_CLENSHAW], "forward_s": secs[pf.FORM_FORWARD]}
-    else:  # the batch: block size (and shapes) tuned per L on an 8-member sample
+    else:  # the batch: block size (and batched-kernel shape) tuned per L on an 8-member sample
         by_L = {}
         for ch in wl.chains:
             by_L.setdefault(ch.L, []).append(ch)

@@ -304,6 +304,19 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
 int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads,
                           int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads,
                           int *rank_incremental, int *xcd_slices);
+/* Launch shape of the batched step kernel of polfed_solve_batch (its
+ * Lanczos filters and FP64 refinement filters) for a launch whose longest
+ * chain has length L, at block width nvec and precision: threads, loads per
+ * lane, workgroups per CU, LDS tables and early loads as in
+ * polfed_set_step_shape (the batched kernel always ranks with the tables and
+ * takes no column slices; the tables go to LDS only when every chain of the
+ * launch has length L).  Separate from the single-chain shape: a batched
+ * launch walks many chains, where the best shape differs.  Without an entry
+ * the built-in single-chain default is used. */
+int polfed_set_batch_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads,
+                           int lpl, int wg_per_cu, int lds_tables, int early_loads);
+int polfed_get_batch_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads,
+                           int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads);
 /* Block size used when opts->block_size is 0 for chains of length L at the
  * given precision and N_ev (the autotuner's choice); without an entry a
  * built-in rule is used (about N_ev/4, capped at 16 in FP64 and 32 in FP32,
@@ -396,7 +409,12 @@ int polfed_solve(polfed_ctx *ctx, const polfed_model *model,
  * 1 <= nev <= dim_r for every model, checked before any work (else
  * POLFED_EINVAL with the outputs untouched).  Window doubling and FP64
  * re-solves as in polfed_solve, each run for the members concerned as a
- * batch of its own. */
+ * batch of its own.  Realisations with one block size and the same J2 != 0
+ * share every filter launch whatever their L (one batched step kernel walks
+ * all their row tiles), and the FP64 refinement filters of the FP32 mode
+ * run batched in the same way.  With opts->block_size = 0 each chain
+ * length takes its own block size (polfed_set_block_size, else the
+ * built-in rule). */
 int polfed_solve_batch(polfed_ctx *ctx, int R, const polfed_model *models,
                        const polfed_opts *opts, int nev, double *evals,
                        double *evecs, double *resid, polfed_info *infos,

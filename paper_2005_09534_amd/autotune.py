@@ -179,7 +179,8 @@ def tune_block(ctx, chains, nev, precision, widths=(4, 8, 16, 32), cache=None, s
     for s in widths:
         if s > nev:  # wider blocks than N_ev waste columns and can hit the column cap
             continue
-        tune_shape(ctx, chains[0], s, precision, cache=shape_cache)
+        if len(models) == 1:
+            tune_shape(ctx, chains[0], s, precision, cache=shape_cache)
 
         def run():
             if len(models) == 1:
@@ -197,25 +198,25 @@ def tune_block(ctx, chains, nev, precision, widths=(4, 8, 16, 32), cache=None, s
         run()  # warm (graph capture, buffers)
         st, t = timed()
         if len(models) > 1:
-            # the batched kernel walks many realisations per launch, where
-            # fewer persistent groups per CU can win (at L = 18, s = 4, FP32:
-            # 4 groups 7% faster than the single chain's 8): re-time the
-            # groups-per-CU choice on the sample batch, keep a change only
-            # when it gains more than 3%
-            base = tuple(ctx.get_step_shape(L, s, precision))
+            # the batched kernel has shapes of its own (a launch walks many
+            # realisations; a single chain's tuned shape, chosen where a
+            # launch is short, can be far off there): re-time the
+            # groups-per-CU choice of the batch shape on the sample batch,
+            # keep a change only when it gains more than 3%
+            base = tuple(ctx.get_batch_shape(L, s, precision))
             best_sh, best_st, best_t = base, st, t
             for wpc in (2, 4, 8, 16):
                 sh = (base[0], base[1], wpc) + base[3:]
                 if wpc == base[2] or wpc * base[0] > 2048:
                     continue
-                ctx.set_step_shape(L, s, precision, *sh)
+                ctx.set_batch_shape(L, s, precision, *sh)
                 run()
                 st_w, t_w = timed()
                 if all(x == pf.OK for x in st_w) and t_w < best_t * 0.97:
                     best_sh, best_st, best_t = sh, st_w, t_w
-            ctx.set_step_shape(L, s, precision, *best_sh)
+            ctx.set_batch_shape(L, s, precision, *best_sh)
             if shape_cache is not None and best_sh != base:
-                shape_cache[_key("shape", L, chains[0].J2, precision, s)] = list(best_sh) + [0.0]
+                shape_cache[_key("bshape", L, chains[0].J2, precision, s)] = list(best_sh) + [0.0]
             st, t = best_st, best_t
         if all(x == pf.OK for x in st):
             times[s] = t
@@ -246,5 +247,7 @@ def apply_cache(ctx, cache):
             sh = [int(t) for t in v[:-1]]
             sh = (sh + [0, 1][len(sh) - 5:])[:7]
             ctx.set_step_shape(int(L), int(x), int(prec), *sh)
+        elif kind == "bshape":
+            ctx.set_batch_shape(int(L), int(x), int(prec), *[int(t) for t in v[:-1]])
         elif kind == "block":
             ctx.set_block_size(int(L), int(prec), int(x), int(v[0]))

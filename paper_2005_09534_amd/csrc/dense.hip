@@ -653,6 +653,10 @@ void sym_eig(hipStream_t st, int n, double *A, double *w, double *V, DevBuf &wor
     k_eye<<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(n, Vw);
     check_launch("k_eye");
   }
+  // up to 128 x 128 the matrix fits one workgroup's LDS: the same sweeps
+  // and stopping rule in a single launch, without a host round trip per
+  // sweep
+  if (n <= kLdsEigMax && sym_eig_batched(st, n, 1, A, Vw, w, V)) return;
   const int m = n + (n & 1);
   const int npair = m / 2;
   const int tp = (npair + kJT - 1) / kJT;

@@ -5,8 +5,9 @@
 namespace polfed {
 
 template void launch_step_batched<double>(hipStream_t, int, const StepArgs<double> &,
-                                          const BatchItem<double> *, int, long long, long long,
-                                          const StepShape &, int);
+                                   const BatchItem<double> *, int, long long, long long,
+                                   long long, const BatchTables &, const StepShape &, int);
+template long long batched_tile_rows<double>(int, const StepShape &);
 template void launch_step<double>(hipStream_t, int, const StepArgs<double> &,
                                   const StepShape &, int);
 

@@ -339,48 +339,75 @@ __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
   }
 }
 
-// Batched Clenshaw step for B realisations of one chain length L (same
-// basis, block width S): realisation i has its own diagonal, coefficients,
-// order K_i and buffers.  At global step j (0 <= j <= Kmax), realisation i
-// is at local step j_i = j - (Kmax - K_i) (idle while j_i < 0), so that all
-// end together; step Kmax is the final combination Y = (c_0 X + H~ b_1 -
-// b_2)/D.  Tiles run realisation-major, so an XCD works through whole
-// realisations.
+// Batched Clenshaw step for B realisations of one block width S (chain
+// lengths may differ): realisation i has its own chain, diagonal,
+// coefficients, order K_i and buffers.  At global step j (0 <= j <= Kmax),
+// realisation i is at local step j_i = j - (Kmax - K_i) (idle while j_i <
+// 0), so that all end together; step Kmax is the final combination Y = (c_0
+// X + H~ b_1 - b_2)/D.  The tiles of all realisations form one range
+// (realisation-major, item i from its tile0), so an XCD works through whole
+// realisations, and short chains share each launch with long ones.
 template <class T, int S, int LPL, bool LDS_TAB, int MAXT, bool EARLY>
 __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const BatchItem<T> *items,
-                                                       int B, long long j, long long Kmax) {
+                                                       int B, long long j, long long Kmax,
+                                                       long long ntiles, BatchTables bt) {
   using C = StepCfg<T, S, LPL>;
   constexpr int VEC = C::VEC, G = C::G, RPW = C::RPW;
   extern __shared__ int32_t s_tab[];
-  const int32_t *tA, *tC;
-  const uint16_t *tB;
-  stage_tables<LDS_TAB, false>(base.tabA, base.tabB, base.binom, base.half, s_tab, tA, tB, tC);
+  const int32_t *tC = base.binom;
+  if (LDS_TAB) {  // every distinct chain length's tables
+    for (int k = 0; k < bt.count; ++k) {
+      const int tsz = 1 << bt.half[k];
+      int32_t *sA = s_tab + bt.off[k];
+      uint16_t *sB = reinterpret_cast<uint16_t *>(sA + tsz);
+      for (int i = threadIdx.x; i < tsz; i += blockDim.x) {
+        sA[i] = bt.A[k][i];
+        sB[i] = bt.B[k][i];
+      }
+    }
+    __syncthreads();
+  }
 
-  const long long n = base.n;
   const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
-  const long long tper = (n + rows_per_iter - 1) / rows_per_iter;
   long long t_begin, t_end, t_step;
   int slice;
-  xcd_tiles(tper * B, 1, slice, t_begin, t_end, t_step);
+  xcd_tiles(ntiles, 1, slice, t_begin, t_end, t_step);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int slot = lane / G;
   const int col = (lane % G) * VEC;
   for (long long t = t_begin; t < t_end; t += t_step) {
-    const int i = (int)(t / tper);
+    // the realisation holding tile t: the last item with tile0 <= t
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].tile0 <= t)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int i = lo;
     const BatchItem<T> it = items[i];
     const long long ji = j - (Kmax - it.K);
     if (!it.active || ji < 0) continue;
-    const long long r = (t - (long long)i * tper) * rows_per_iter + (long long)wave * RPW + slot;
-    if (r >= n) continue;
+    const long long r = (t - it.tile0) * rows_per_iter + (long long)wave * RPW + slot;
+    if (r >= it.n) continue;
     StepArgs<T> a = base;
+    a.states = it.states;
+    a.n = it.n;
+    a.L = it.L;
+    a.half = it.half;
+    a.lomask = it.lomask;
+    a.fullmask = it.fullmask;
     a.dt = it.dt;
-    const size_t blk = (size_t)n * S;
+    const size_t blk = (size_t)it.n * S;
     T *bufs[3] = {it.buf, it.buf + blk, it.buf + 2 * blk};
-    a.ldv = a.ldw = a.ldo = a.ldx = S;
+    a.ldv = a.ldw = S;
+    a.ldx = it.ldx;
     if (j < Kmax) {
       const long long k = it.K - ji;
       a.out = bufs[ji % 3];
+      a.ldo = S;
       a.V = (ji >= 1) ? bufs[(ji - 1) % 3] : nullptr;
       a.W = (ji >= 2) ? bufs[(ji - 2) % 3] : nullptr;
       const double ck = it.coef[k];
@@ -392,6 +419,7 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
       a.gamma = T(-1);
     } else {
       a.out = it.Y;
+      a.ldo = it.ldy;
       a.X = it.X;
       a.alpha = (T)(it.coef[0] * it.Dinv);
       a.V = (it.K >= 1) ? bufs[(it.K - 1) % 3] : nullptr;
@@ -401,7 +429,13 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
       a.w2 = (T)(0.5 * (double)it.w2 * it.Dinv);
       a.gamma = (T)(-it.Dinv);
     }
-    step_row<T, S, LPL, EARLY, 0>(a, r, col, tA, tB, tC);
+    if (LDS_TAB) {
+      const int32_t *tA = s_tab + bt.off[it.tab];
+      step_row<T, S, LPL, EARLY, 0>(a, r, col, tA,
+                                    reinterpret_cast<const uint16_t *>(tA + (1 << it.half)), tC);
+    } else {
+      step_row<T, S, LPL, EARLY, 0>(a, r, col, it.tabA, it.tabB, tC);
+    }
   }
 }
 
@@ -467,7 +501,8 @@ struct BatchedLaunch {
   const StepArgs<T> &a;
   const BatchItem<T> *items;
   int B;
-  long long j, Kmax, nwg;
+  long long j, Kmax, ntiles, nwg;
+  const BatchTables &bt;
   int threads;
   size_t shm;
   template <bool LDS_TAB, int MAXT, bool EARLY, int RM>
@@ -477,7 +512,7 @@ struct BatchedLaunch {
           reinterpret_cast<const void *>(k_step_batched<T, S, LPL, LDS_TAB, MAXT, EARLY>),
           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     k_step_batched<T, S, LPL, LDS_TAB, MAXT, EARLY>
-        <<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a, items, B, j, Kmax);
+        <<<(unsigned)nwg, threads, LDS_TAB ? shm : 0, st>>>(a, items, B, j, Kmax, ntiles, bt);
   }
 };
 
@@ -508,18 +543,16 @@ static void launch_step_s(hipStream_t st, const StepArgs<T> &a0, const StepShape
 
 template <class T, int S, int LPL>
 static void launch_batched_s(hipStream_t st, const StepArgs<T> &a, const BatchItem<T> *items,
-                             int B, long long j, long long Kmax, const StepShape &shape,
-                             int num_cu) {
-  using C = StepCfg<T, S, LPL>;
+                             int B, long long j, long long Kmax, long long ntiles,
+                             const BatchTables &bt, const StepShape &shape, int num_cu) {
   const int threads = shape.threads;
-  const long long rows_per_iter = (long long)(threads / 64) * C::RPW;
-  const long long tiles = ((a.n + rows_per_iter - 1) / rows_per_iter) * B;
-  long long nwg = std::min((long long)num_cu * shape.wg_per_cu, tiles);
+  long long nwg = std::min((long long)num_cu * shape.wg_per_cu, ntiles);
   nwg = ((nwg + 7) / 8) * 8;
-  const bool lds = shape.lds_tables && a.L <= kMaxLdsTableL;
-  const size_t shm = lds ? (size_t)6 * ((size_t)1 << a.half) : 0;
+  const bool lds = shape.lds_tables && bt.count > 0;
+  const size_t shm = lds ? sizeof(int32_t) * (size_t)bt.ints : 0;
   dispatch_shape<false>(lds, threads, shape.early_loads != 0, 0,
-                        BatchedLaunch<T, S, LPL>{st, a, items, B, j, Kmax, nwg, threads, shm});
+                        BatchedLaunch<T, S, LPL>{st, a, items, B, j, Kmax, ntiles, nwg, bt,
+                                                 threads, shm});
   check_launch("k_step_batched");
 }
 
@@ -566,26 +599,30 @@ void launch_step(hipStream_t st, int S, const StepArgs<T> &a0, const StepShape &
 
 template <class T>
 void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const BatchItem<T> *items,
-                         int B, long long j, long long Kmax, const StepShape &shape, int num_cu) {
-  if (a.n <= 0 || B <= 0) return;
+                         int B, long long j, long long Kmax, long long total_tiles,
+                         const BatchTables &tables, const StepShape &shape, int num_cu) {
+  if (total_tiles <= 0 || B <= 0) return;
   if (shape.threads != 256 && shape.threads != 512 && shape.threads != 1024)
     throw Error(POLFED_EINVAL, "step kernel: threads must be 256, 512 or 1024");
-#define PF_BATCH_CASE(SS)                                                              \
-  case SS: {                                                                           \
-    constexpr int M = max_lpl<T, SS>();                                                \
-    const int lpl = std::min(shape.lpl, M);                                            \
-    if constexpr (M >= 4)                                                              \
-      if (lpl == 4) {                                                                  \
-        launch_batched_s<T, SS, 4>(st, a, items, B, j, Kmax, shape, num_cu);           \
-        break;                                                                         \
-      }                                                                                \
-    if constexpr (M >= 2)                                                              \
-      if (lpl == 2) {                                                                  \
-        launch_batched_s<T, SS, 2>(st, a, items, B, j, Kmax, shape, num_cu);           \
-        break;                                                                         \
-      }                                                                                \
-    launch_batched_s<T, SS, 1>(st, a, items, B, j, Kmax, shape, num_cu);               \
-    break;                                                                             \
+#define PF_BATCH_CASE(SS)                                                                  \
+  case SS: {                                                                               \
+    constexpr int M = max_lpl<T, SS>();                                                    \
+    const int lpl = std::min(shape.lpl, M);                                                \
+    if constexpr (M >= 4)                                                                  \
+      if (lpl == 4) {                                                                      \
+        launch_batched_s<T, SS, 4>(st, a, items, B, j, Kmax, total_tiles, tables, shape,   \
+                                   num_cu);                                                \
+        break;                                                                             \
+      }                                                                                    \
+    if constexpr (M >= 2)                                                                  \
+      if (lpl == 2) {                                                                      \
+        launch_batched_s<T, SS, 2>(st, a, items, B, j, Kmax, total_tiles, tables, shape,   \
+                                   num_cu);                                                \
+        break;                                                                             \
+      }                                                                                    \
+    launch_batched_s<T, SS, 1>(st, a, items, B, j, Kmax, total_tiles, tables, shape,       \
+                               num_cu);                                                    \
+    break;                                                                                 \
   }
   switch (S) {
     PF_BATCH_CASE(1)
@@ -598,6 +635,31 @@ void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const Batc
     default: throw Error(POLFED_EINVAL, "block width must be a power of two in [1, 64]");
   }
 #undef PF_BATCH_CASE
+}
+
+// Rows per tile of the batched kernel: the workgroup's waves times the rows
+// a wave covers at the loads per lane the launcher picks for this width.
+template <class T>
+long long batched_tile_rows(int S, const StepShape &shape) {
+  auto rows = [&](auto s_c) -> long long {
+    constexpr int SS = decltype(s_c)::value;
+    constexpr int M = max_lpl<T, SS>();
+    const int lpl = std::min(shape.lpl, M);
+    const int rpw = (lpl >= 4 && M >= 4) ? StepCfg<T, SS, (M >= 4 ? 4 : 1)>::RPW
+                    : (lpl >= 2 && M >= 2) ? StepCfg<T, SS, (M >= 2 ? 2 : 1)>::RPW
+                                           : StepCfg<T, SS, 1>::RPW;
+    return (long long)(shape.threads / 64) * rpw;
+  };
+  switch (S) {
+    case 1: return rows(std::integral_constant<int, 1>{});
+    case 2: return rows(std::integral_constant<int, 2>{});
+    case 4: return rows(std::integral_constant<int, 4>{});
+    case 8: return rows(std::integral_constant<int, 8>{});
+    case 16: return rows(std::integral_constant<int, 16>{});
+    case 32: return rows(std::integral_constant<int, 32>{});
+    case 64: return rows(std::integral_constant<int, 64>{});
+    default: throw Error(POLFED_EINVAL, "block width must be a power of two in [1, 64]");
+  }
 }
 
 }  // namespace polfed

@@ -50,6 +50,7 @@ struct DevBuf {
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf();
   void *ensure(size_t nbytes);  // contents not preserved on growth
+  void release();               // free now (after the device is done with it)
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -168,23 +169,59 @@ struct StepShape {
 template <class T>
 void launch_step(hipStream_t st, int S, const StepArgs<T> &a, const StepShape &shape, int num_cu);
 
-// One realisation of a batched filter (device-resident descriptor).
+// One realisation of a batched filter (device-resident descriptor).  The
+// realisations of one launch share the block width and whether J2 != 0;
+// each brings its own chain length and basis.
 template <class T>
 struct BatchItem {
   const T *dt;         // a d + b
-  const T *X;          // n x S input block
-  T *buf;              // 3 n x S recurrence buffers
-  T *Y;                // n x S output
+  const T *X;          // n x S input block (leading dimension ldx)
+  T *buf;              // 3 n x S recurrence buffers (leading dimension S)
+  T *Y;                // n x S output (leading dimension ldy)
   const double *coef;  // c_0 .. c_K (device)
   double Dinv;         // 1 / D
   T w1, w2;            // a J1, a J2
   long long K;
   int active;
+  // the realisation's chain: Sz=0 states and rank tables, dimension, L
+  const uint32_t *states;
+  const int32_t *tabA;
+  const uint16_t *tabB;
+  long long n;
+  int L, half;
+  uint32_t lomask, fullmask;
+  long long ldx, ldy;
+  // first row tile of this realisation in the launch's tile range (tiles of
+  // batched_tile_rows rows, realisations in item order)
+  long long tile0;
+  int tab;  // its entry in the launch's BatchTables (when staged in LDS)
 };
 
+// The distinct rank tables of a batched launch (one per chain length), all
+// staged in LDS: set k at int32 offset off[k] (tabA, then tabB as uint16).
+// count = 0: every realisation reads its own tables from global memory.
+constexpr int kMaxBatchTables = 8;
+struct BatchTables {
+  const int32_t *A[kMaxBatchTables];
+  const uint16_t *B[kMaxBatchTables];
+  int half[kMaxBatchTables];
+  int off[kMaxBatchTables];
+  int count;
+  int ints;  // LDS size in int32 words
+};
+
+// Rows per tile of the batched step kernel for this width and shape.
+template <class T>
+long long batched_tile_rows(int S, const StepShape &shape);
+
+// One batched Clenshaw step j (0..Kmax) for the B realisations of items
+// (device array, tile0 filled for batched_tile_rows; total_tiles = the
+// tiles of all of them).  a: the launch's common arguments (has_j2, binom);
+// tables: the rank tables staged in LDS (count 0: none).
 template <class T>
 void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const BatchItem<T> *items,
-                         int B, long long j, long long Kmax, const StepShape &shape, int num_cu);
+                         int B, long long j, long long Kmax, long long total_tiles,
+                         const BatchTables &tables, const StepShape &shape, int num_cu);
 // Built-in default shape (used when the context holds no tuned entry).
 StepShape default_shape(int L, int S, bool fp32);
 
@@ -351,6 +388,9 @@ struct polfed_ctx {
   // launch shapes of the step kernel chosen by the autotuner, keyed by
   // (L, block width, precision bytes)
   std::map<std::tuple<int, int, int>, polfed::StepShape> shapes;
+  // launch shapes of the batched step kernel (same key); its rank mode is
+  // always the tables and its column slices 1
+  std::map<std::tuple<int, int, int>, polfed::StepShape> batch_shapes;
   // block sizes chosen by the autotuner, keyed by (L, precision, nev)
   std::map<std::tuple<int, int, int>, int> blocks;
   // cached HIP graph of one whole filter application (K+1 step launches),

@@ -26,6 +26,7 @@
 #include <chrono>
 #include <iterator>
 #include <map>
+#include <set>
 #include <memory>
 #include <cmath>
 #include <cstdio>
@@ -591,6 +592,26 @@ struct Realization {
   void check_finish(const double *th, const double *Vt);
   void check_single();  // prepare, sym_eig, finish
   int finalize(double *evals, double *evecs, double *resid, polfed_info *info);
+  // finalize in phases, for the batch driver (which runs the refinement
+  // filters of its members as batched launches): the Rayleigh-Ritz step on
+  // the final T_m's candidates, returning whether an FP64 refinement pass is
+  // wanted; a pass's input Vn and coefficients; the pass's filter UR =
+  // P^{K_r}(H~) Vn alone; its orthonormalisation and Rayleigh-Ritz,
+  // returning whether another pass is wanted; the outputs.
+  bool fin_begin();
+  void refine_prepare();
+  void refine_filter_single();
+  bool refine_finish();
+  int fin_end(double *evals, double *evecs, double *resid, polfed_info *info);
+  // state of the phases: the Rayleigh-Ritz space UR, its Ritz vectors WR,
+  // a pass's input Vn, the returned vectors Vout, and H~'s diagonal in FP64
+  DevBuf URb, WRb, Vnb, Voutb, dt64b;
+  int nc = 0, q = 0, qpad = 0, ldr = 0, ldo = 0, nout = 0, passes = 0;
+  bool converged_fin = false;
+  std::vector<double> Efin, Esel, rres, coef_r;
+  double D_r = 1.0, rmax = 0.0, refine_target = 0.0, t3 = 0.0, tr0 = 0.0;
+  double t_refine = 0.0, refine_bytes = 0.0, rr_apps = 0.0, ctx_gpu0 = 0.0, ctx_launch0 = 0.0;
+  long long K_r = 0;
   // The filter window held fewer than nev Ritz values with theta >= p at
   // the last check: the order K from the Gaussian DOS made the main lobe too
   // narrow for nev eigenvalues (a DOS that is low at the target, as in short
@@ -599,6 +620,10 @@ struct Realization {
   bool window_short() const { return o.K <= 0 && above < nev; }
 
  private:
+  double finish(const double *X, long long ldx, const std::vector<int> &idx,
+                const std::vector<double> &Ev);
+  std::vector<int> nearest(const std::vector<double> &E, const std::vector<char> &ok, int k) const;
+  double rayleigh_ritz(int k);
   int cholqr2(double *X, double *out, long long ldo);
   void refill_block(const double *Uorig, double *out, long long ldo, int pc, int j);
 };
@@ -940,16 +965,103 @@ void Realization<T>::check_single() {
   check_finish(th, Vt);
 }
 
+// Vout (n x nout, ld ldo) <- columns idx of X (ld ldx); then normalise, fix
+// signs and compute ||H v - E v||.  Returns the largest residual.
 template <class T>
-int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed_info *info) {
+double Realization<T>::finish(const double *X, long long ldx, const std::vector<int> &idx,
+                              const std::vector<double> &Ev) {
+  hipStream_t st = ctx->stream;
+  DevBuf &partials = ctx->buf("partials");
+  double *Vout = Voutb.as<double>();
+  double *HV = static_cast<double *>(ctx->buf("HV").ensure(sizeof(double) * (size_t)n * ldo));
+  double *vecs = static_cast<double *>(ctx->buf("vecs").ensure(sizeof(double) * 4 * (size_t)ldo));
+  double *nrm = vecs, *Ed = vecs + ldo, *rd = vecs + 2 * ldo, *sg = vecs + 3 * ldo;
+  int *didx = static_cast<int *>(ctx->buf("idx").ensure(sizeof(int) * (size_t)(P + 64) * 2));
+  nout = (int)idx.size();
+  Esel = Ev;
+  rres.assign(nout, 0.0);
+  PF_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int) * nout, hipMemcpyHostToDevice, st));
+  launch_gather_cols(st, n, nout, X, ldx, didx, Vout, ldo);
+  launch_colnorms(st, n, nout, Vout, ldo, nrm, partials, ctx->num_cu);
+  std::vector<double> hn(nout);
+  PF_HIP(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
+  for (int i = 0; i < nout; ++i) hn[i] = 1.0 / hn[i];
+  PF_HIP(hipMemcpyAsync(nrm, hn.data(), sizeof(double) * nout, hipMemcpyHostToDevice, st));
+  launch_scale_cols(st, n, nout, Vout, ldo, nrm);
+  launch_sign_factors(st, n, nout, Vout, ldo, sg, partials, ctx->num_cu);
+  launch_scale_cols(st, n, nout, Vout, ldo, sg);
+  apply_op<double>(ctx, c, c.diag.as<double>(), 0.5 * c.J1, 0.5 * c.J2, Vout, ldo, HV, ldo, nout,
+                   false);
+  rr_apps += nout;
+  PF_HIP(hipMemcpyAsync(Ed, Esel.data(), sizeof(double) * nout, hipMemcpyHostToDevice, st));
+  launch_resid_norms(st, n, nout, HV, ldo, Vout, ldo, Ed, rd, partials, ctx->num_cu);
+  PF_HIP(hipMemcpyAsync(rres.data(), rd, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
+  double rm = 0.0;
+  for (int i = 0; i < nout; ++i) rm = std::max(rm, rres[i]);
+  return rm;
+}
+
+// indices of the k values of E nearest sigma_H (ties -> lower E), taken
+// from those with ok[i]; returned ascending in E
+template <class T>
+std::vector<int> Realization<T>::nearest(const std::vector<double> &E,
+                                         const std::vector<char> &ok, int k) const {
+  std::vector<int> ord;
+  for (int i = 0; i < (int)E.size(); ++i)
+    if (ok[i]) ord.push_back(i);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    const double dx = std::fabs(E[x] - sigma_H), dy = std::fabs(E[y] - sigma_H);
+    if (dx != dy) return dx < dy;
+    return E[x] < E[y];
+  });
+  if ((int)ord.size() > k) ord.resize(k);
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return E[x] < E[y]; });
+  return ord;
+}
+
+// Rayleigh-Ritz of H~ on span(UR[:, :k]) (orthonormal): WR = UR Y, the nev
+// nearest the target selected and finished; returns their largest residual.
+template <class T>
+double Realization<T>::rayleigh_ritz(int k) {
   hipStream_t st = ctx->stream;
   DevBuf &partials = ctx->buf("partials");
   DevBuf &eigwork = ctx->buf("eigwork");
+  double *UR = URb.as<double>(), *WR = WRb.as<double>();
+  double *Gr = static_cast<double *>(ctx->buf("Gr").ensure(sizeof(double) * (size_t)ldr * ldr * 3 + 16));
+  double *Yr = Gr + (size_t)ldr * ldr;
+  double *epsd = static_cast<double *>(ctx->buf("epsd").ensure(sizeof(double) * (size_t)ldr));
+  apply_op<double>(ctx, c, dt64b.as<double>(), 0.5 * a * c.J1, 0.5 * a * c.J2, UR, ldr, WR, ldr, k,
+                   false);
+  rr_apps += k;
+  launch_gram(st, n, k, k, UR, ldr, WR, ldr, Gr, k, partials, ctx->num_cu);
+  launch_symmetrize(st, k, Gr, k);
+  sym_eig(st, k, Gr, epsd, Yr, eigwork);
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int w = std::min(64, k - c0);
+    launch_update(st, n, k, w, 1.0, UR, ldr, Yr + c0, k, 0.0, WR + c0, ldr);
+  }
+  std::vector<double> eps(k);
+  PF_HIP(hipMemcpyAsync(eps.data(), epsd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  PF_HIP(hipStreamSynchronize(st));
+  Efin.resize(k);
+  for (int i = 0; i < k; ++i) Efin[i] = (eps[i] - b) / a;
+  const std::vector<int> sel = nearest(Efin, std::vector<char>(k, 1), nev);
+  std::vector<double> Ev;
+  for (int i : sel) Ev.push_back(Efin[i]);
+  return finish(WR, ldr, sel, Ev);
+}
+
+// The final T_m's eigenpairs, the Rayleigh-Ritz step on the candidates and
+// the selection of the nev nearest the target.  Returns whether an FP64
+// refinement pass is wanted (FP32 filter, residuals above its target).
+template <class T>
+bool Realization<T>::fin_begin() {
+  hipStream_t st = ctx->stream;
+  DevBuf &eigwork = ctx->buf("eigwork");
   const int ms = m_done * s;
-  const bool converged = nconv >= nev;
-  polfed_info inf;
-  std::memset(&inf, 0, sizeof(inf));
-  inf.t_bounds = t_bounds;
+  converged_fin = nconv >= nev;
   double *Qp = Q();
   // the eigenpairs of the final T_m
   double *Tw = static_cast<double *>(ctx->buf("Tw").ensure(sizeof(double) * (size_t)P * P));
@@ -970,232 +1082,188 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
   PF_HIP(hipStreamSynchronize(st));
   // 7: Rayleigh-Ritz of H~, selection of the nev nearest the target, and
   // residuals with the unscaled H
-  double t3 = now_s();
-  double *dt64 = static_cast<double *>(ctx->buf("dt64").ensure(sizeof(double) * n));
-  launch_scaled_diag<double>(st, n, c.diag.as<double>(), a, b, dt64);
+  t3 = now_s();
+  ctx_gpu0 = ctx->filter_gpu_s;
+  ctx_launch0 = ctx->filter_launches;
+  dt64b.ensure(sizeof(double) * n);
+  launch_scaled_diag<double>(st, n, c.diag.as<double>(), a, b, dt64b.as<double>());
   const int nout_max = std::min<long long>(nev, ms);
-  const int ldo = ((nout_max + 7) / 8) * 8;
-  double *Vout = static_cast<double *>(ctx->buf("Vout").ensure(sizeof(double) * (size_t)n * ldo));
-  double *HV = static_cast<double *>(ctx->buf("HV").ensure(sizeof(double) * (size_t)n * ldo));
-  double *vecs = static_cast<double *>(ctx->buf("vecs").ensure(sizeof(double) * 4 * (size_t)ldo));
-  double *nrm = vecs, *Ed = vecs + ldo, *rd = vecs + 2 * ldo, *sg = vecs + 3 * ldo;
+  ldo = ((nout_max + 7) / 8) * 8;
+  Voutb.ensure(sizeof(double) * (size_t)n * ldo);
   int *didx = static_cast<int *>(ctx->buf("idx").ensure(sizeof(int) * (size_t)(P + 64) * 2));
-  std::vector<double> Esel, r;
-  double refine_bytes = 0.0, t_refine = 0.0, rr_apps = 0.0;
-  const double ctx_gpu0 = ctx->filter_gpu_s, ctx_launch0 = ctx->filter_launches;
-  int passes = 0, nout = 0;
-  const bool verbose = std::getenv("POLFED_VERBOSE") != nullptr;
 
-  // Vout (n x nout, ld ldo) <- columns idx of X (ld ldx); then normalise,
-  // fix signs and compute ||H v - E v||.  Returns the largest residual.
-  auto finish = [&](const double *X, long long ldx, const std::vector<int> &idx,
-                    const std::vector<double> &Ev) -> double {
-    nout = (int)idx.size();
-    Esel = Ev;
-    r.assign(nout, 0.0);
-    PF_HIP(hipMemcpyAsync(didx, idx.data(), sizeof(int) * nout, hipMemcpyHostToDevice, st));
-    launch_gather_cols(st, n, nout, X, ldx, didx, Vout, ldo);
-    launch_colnorms(st, n, nout, Vout, ldo, nrm, partials, ctx->num_cu);
-    std::vector<double> hn(nout);
-    PF_HIP(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
-    PF_HIP(hipStreamSynchronize(st));
-    for (int i = 0; i < nout; ++i) hn[i] = 1.0 / hn[i];
-    PF_HIP(hipMemcpyAsync(nrm, hn.data(), sizeof(double) * nout, hipMemcpyHostToDevice, st));
-    launch_scale_cols(st, n, nout, Vout, ldo, nrm);
-    launch_sign_factors(st, n, nout, Vout, ldo, sg, partials, ctx->num_cu);
-    launch_scale_cols(st, n, nout, Vout, ldo, sg);
-    apply_op<double>(ctx, c, c.diag.as<double>(), 0.5 * c.J1, 0.5 * c.J2, Vout, ldo, HV, ldo,
-                     nout, false);
-    rr_apps += nout;
-    PF_HIP(hipMemcpyAsync(Ed, Esel.data(), sizeof(double) * nout, hipMemcpyHostToDevice, st));
-    launch_resid_norms(st, n, nout, HV, ldo, Vout, ldo, Ed, rd, partials, ctx->num_cu);
-    PF_HIP(hipMemcpyAsync(r.data(), rd, sizeof(double) * nout, hipMemcpyDeviceToHost, st));
-    PF_HIP(hipStreamSynchronize(st));
-    double rmax = 0.0;
-    for (int i = 0; i < nout; ++i) rmax = std::max(rmax, r[i]);
-    return rmax;
-  };
-  // indices of the k values of E nearest sigma_H (ties -> lower E), taken
-  // from those with ok[i]; returned ascending in E
-  auto nearest = [&](const std::vector<double> &E, const std::vector<char> &ok, int k) {
-    std::vector<int> ord;
-    for (int i = 0; i < (int)E.size(); ++i)
-      if (ok[i]) ord.push_back(i);
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
-      const double dx = std::fabs(E[x] - sigma_H), dy = std::fabs(E[y] - sigma_H);
-      if (dx != dy) return dx < dy;
-      return E[x] < E[y];
-    });
-    if ((int)ord.size() > k) ord.resize(k);
-    std::sort(ord.begin(), ord.end(), [&](int x, int y) { return E[x] < E[y]; });
-    return ord;
-  };
-
-  {
-    // candidates: theta >= p (else the nev largest theta); their Ritz vectors
-    // Qm t_i span the Rayleigh-Ritz space
-    std::vector<int> cand;
-    for (int i = 0; i < ms; ++i)
-      if (theta[i] >= o.p) cand.push_back(i);
-    // at least nev candidates (the nev largest theta when fewer pass p)
-    const int want = nev;
-    if ((int)cand.size() < want) {
-      cand.clear();
-      for (int i = ms - 1; i >= 0 && (int)cand.size() < want; --i) cand.push_back(i);
-      std::sort(cand.begin(), cand.end());
-    }
-    const int nc = (int)cand.size();
-    // refined columns (FP32 mode): all candidates, so that every in-window
-    // error direction lies in the Rayleigh-Ritz space; padded to kernel
-    // widths: whole 64-column launches, then the remainder rounded up to a
-    // power of two
-    const int q = nc;
-    int qpad = 64 * (q / 64);
-    if (q % 64) {
-      int w = 1;
-      while (w < q % 64) w *= 2;
-      qpad += w;
-    }
-    const int ldr = std::max(((nc + 7) / 8) * 8, qpad);
-    PF_HIP(hipMemcpyAsync(didx, cand.data(), sizeof(int) * nc, hipMemcpyHostToDevice, st));
-    double *Tsel = static_cast<double *>(ctx->buf("Tsel").ensure(sizeof(double) * (size_t)ms * ldr));
-    launch_gather_cols(st, ms, nc, Vt, ms, didx, Tsel, ldr);
-    double *UR = static_cast<double *>(ctx->buf("UR").ensure(sizeof(double) * (size_t)n * ldr));
-    double *WR = static_cast<double *>(ctx->buf("WR").ensure(sizeof(double) * (size_t)n * ldr));
-    for (int c0 = 0; c0 < nc; c0 += 64) {
-      const int w = std::min(64, nc - c0);
-      launch_update(st, n, ms, w, 1.0, Qp, P, Tsel + c0, ldr, 0.0, UR + c0, ldr);
-    }
-    double *Gr = static_cast<double *>(ctx->buf("Gr").ensure(sizeof(double) * (size_t)ldr * ldr * 3 + 16));
-    double *Yr = Gr + (size_t)ldr * ldr;
-    double *Mr = Yr + (size_t)ldr * ldr;
-    double *epsd = static_cast<double *>(ctx->buf("epsd").ensure(sizeof(double) * (size_t)ldr));
-    std::vector<double> E;
-    std::vector<int> sel;
-    // Rayleigh-Ritz of H~ on span(UR[:, :k]) (orthonormal): WR = UR Y
-    auto rayleigh_ritz = [&](int k) {
-      apply_op<double>(ctx, c, dt64, 0.5 * a * c.J1, 0.5 * a * c.J2, UR, ldr, WR, ldr, k, false);
-      rr_apps += k;
-      launch_gram(st, n, k, k, UR, ldr, WR, ldr, Gr, k, partials, ctx->num_cu);
-      launch_symmetrize(st, k, Gr, k);
-      sym_eig(st, k, Gr, epsd, Yr, eigwork);
-      for (int c0 = 0; c0 < k; c0 += 64) {
-        const int w = std::min(64, k - c0);
-        launch_update(st, n, k, w, 1.0, UR, ldr, Yr + c0, k, 0.0, WR + c0, ldr);
-      }
-      std::vector<double> eps(k);
-      PF_HIP(hipMemcpyAsync(eps.data(), epsd, sizeof(double) * k, hipMemcpyDeviceToHost, st));
-      PF_HIP(hipStreamSynchronize(st));
-      E.resize(k);
-      for (int i = 0; i < k; ++i) E[i] = (eps[i] - b) / a;
-      sel = nearest(E, std::vector<char>(k, 1), nev);
-      std::vector<double> Ev;
-      for (int i : sel) Ev.push_back(E[i]);
-      return finish(WR, ldr, sel, Ev);
-    };
-    double rmax = rayleigh_ritz(nc);
-    if (verbose) fprintf(stderr, "[polfed] rr: %d candidates, max resid / ||H|| = %.3e\n", nc, rmax / normH);
-
-    // FP64 refinement of the FP32-filter mode.  The FP32 rounding of the
-    // recurrence leaves errors ~eps32 sqrt(K) in the Ritz vectors, spread
-    // over the whole spectrum.  Subspace iteration with the FP64 filter
-    // P^{K_r}(H~) on the q candidate Ritz vectors damps a component at
-    // angular distance u from the target by ~1/(K_r u) relative to the wanted
-    // ones, so a short filter removes that spread (K_r = K/4 first); the
-    // slower near-window part (damped by theta_k / theta_i per pass) is small
-    // because the FP32 Lanczos ran to convergence at the rounding level.
-    // Rayleigh-Ritz on the filtered span removes the mixing among candidates.
-    // K_r = K/4, K/2, then K, at most 8 passes; target 8e-9 ||H|| (or tol if
-    // looser), under the 1e-8 ||H|| bar for returned residuals (the returned
-    // residuals are recomputed exactly, so the bar is met, not estimated).
-    const double target = std::max(o.tol, 8e-9) * normH;
-    const long long K_ref = K;
-    long long K_r = std::max<long long>(16, K_ref / 4);
-    std::vector<double> coef_r;
-    double D_r = 1.0;
-    double *Vn = static_cast<double *>(ctx->buf("Vn").ensure(sizeof(double) * (size_t)n * ldr));
-    double *cheb64 = nullptr;
-    bool zeroed = false;
-    while (fp32 && rmax > target && passes < 8) {
-      const double tr0 = now_s();
-      if (!cheb64)
-        cheb64 = static_cast<double *>(ctx->buf("cheb64").ensure(sizeof(double) * 3 * (size_t)n * 64));
-      if (!zeroed) {  // padding columns stay zero
-        launch_fill(st, Vn, (long long)n * ldr, 0.0);
-        zeroed = true;
-      }
-      std::vector<int> near = nearest(E, std::vector<char>(E.size(), 1), q);
-      PF_HIP(hipMemcpyAsync(didx, near.data(), sizeof(int) * q, hipMemcpyHostToDevice, st));
-      launch_gather_cols(st, n, q, WR, ldr, didx, Vn, ldr);
-      cheb_coeffs(sigma, K_r, coef_r, D_r);
-      for (int c0 = 0; c0 < qpad; c0 += 64) {
-        const int w = std::min(64, qpad - c0);  // 64, or the power-of-two remainder
-        run_filter<double>(ctx, c, dt64, a, w, Vn + c0, ldr, UR + c0, ldr, K_r, coef_r, D_r, cheb64,
-                           false, &refine_bytes, false);
-      }
-      rr_apps += (double)(K_r + 1) * q;
-      // SVQB orthonormalisation of UR[:, :q] (twice): UR <- UR W Lambda^{-1/2}
-      for (int it = 0; it < 2; ++it) {
-        launch_gram(st, n, q, q, UR, ldr, UR, ldr, Gr, q, partials, ctx->num_cu);
-        launch_symmetrize(st, q, Gr, q);
-        sym_eig(st, q, Gr, epsd, Yr, eigwork);
-        std::vector<double> lam(q), W((size_t)q * q);
-        PF_HIP(hipMemcpyAsync(lam.data(), epsd, sizeof(double) * q, hipMemcpyDeviceToHost, st));
-        PF_HIP(hipMemcpyAsync(W.data(), Yr, sizeof(double) * q * q, hipMemcpyDeviceToHost, st));
-        PF_HIP(hipStreamSynchronize(st));
-        for (int i = 0; i < q; ++i) {
-          const double f = (lam[i] > 1e-28 * lam[q - 1]) ? 1.0 / std::sqrt(lam[i]) : 0.0;
-          for (int k = 0; k < q; ++k) W[(size_t)k * q + i] *= f;
-        }
-        PF_HIP(hipMemcpyAsync(Mr, W.data(), sizeof(double) * q * q, hipMemcpyHostToDevice, st));
-        for (int c0 = 0; c0 < q; c0 += 64) {
-          const int w = std::min(64, q - c0);
-          launch_update(st, n, q, w, 1.0, UR, ldr, Mr + c0, q, 0.0, WR + c0, ldr);
-        }
-        PF_HIP(hipMemcpy2DAsync(UR, sizeof(double) * ldr, WR, sizeof(double) * ldr,
-                                sizeof(double) * q, n, hipMemcpyDeviceToDevice, st));
-      }
-      PF_HIP(hipStreamSynchronize(st));
-      t_refine += now_s() - tr0;
-      ++passes;
-      const double rprev = rmax;
-      rmax = rayleigh_ritz(q);
-      if (verbose)
-        fprintf(stderr, "[polfed] refine pass %d: K_r %lld, %d vectors, max resid / ||H|| = %.3e\n",
-                passes, K_r, q, rmax / normH);
-      // a pass at (about) the full order K that gains less than 10% has
-      // stalled (a wanted direction missing from, or barely separated
-      // within, the refined span); more passes would not reach the target,
-      // and the caller's FP64 re-solve is cheaper than running them out
-      if (2 * K_r > K_ref && rmax > 0.9 * rprev) break;
-      K_r = std::min<long long>(2 * K_r, K_ref);
-    }
+  // candidates: theta >= p (else the nev largest theta); their Ritz vectors
+  // Qm t_i span the Rayleigh-Ritz space
+  std::vector<int> cand;
+  for (int i = 0; i < ms; ++i)
+    if (theta[i] >= o.p) cand.push_back(i);
+  // at least nev candidates (the nev largest theta when fewer pass p)
+  const int want = nev;
+  if ((int)cand.size() < want) {
+    cand.clear();
+    for (int i = ms - 1; i >= 0 && (int)cand.size() < want; --i) cand.push_back(i);
+    std::sort(cand.begin(), cand.end());
   }
+  nc = (int)cand.size();
+  // refined columns (FP32 mode): all candidates, so that every in-window
+  // error direction lies in the Rayleigh-Ritz space; padded to kernel
+  // widths: whole 64-column launches, then the remainder rounded up to a
+  // power of two
+  q = nc;
+  qpad = 64 * (q / 64);
+  if (q % 64) {
+    int w = 1;
+    while (w < q % 64) w *= 2;
+    qpad += w;
+  }
+  ldr = std::max(((nc + 7) / 8) * 8, qpad);
+  PF_HIP(hipMemcpyAsync(didx, cand.data(), sizeof(int) * nc, hipMemcpyHostToDevice, st));
+  double *Tsel = static_cast<double *>(ctx->buf("Tsel").ensure(sizeof(double) * (size_t)ms * ldr));
+  launch_gather_cols(st, ms, nc, Vt, ms, didx, Tsel, ldr);
+  URb.ensure(sizeof(double) * (size_t)n * ldr);
+  WRb.ensure(sizeof(double) * (size_t)n * ldr);
+  for (int c0 = 0; c0 < nc; c0 += 64) {
+    const int w = std::min(64, nc - c0);
+    launch_update(st, n, ms, w, 1.0, Qp, P, Tsel + c0, ldr, 0.0, URb.as<double>() + c0, ldr);
+  }
+  rmax = rayleigh_ritz(nc);
+  if (std::getenv("POLFED_VERBOSE"))
+    fprintf(stderr, "[polfed] rr: %d candidates, max resid / ||H|| = %.3e\n", nc, rmax / normH);
+  // the Lanczos basis and T_m are no longer needed (a batch holds many)
+  Qb.release();
+  Tmb.release();
+
+  // FP64 refinement of the FP32-filter mode.  The FP32 rounding of the
+  // recurrence leaves errors ~eps32 sqrt(K) in the Ritz vectors, spread
+  // over the whole spectrum.  Subspace iteration with the FP64 filter
+  // P^{K_r}(H~) on the q candidate Ritz vectors damps a component at
+  // angular distance u from the target by ~1/(K_r u) relative to the wanted
+  // ones, so a short filter removes that spread (K_r = K/4 first); the
+  // slower near-window part (damped by theta_k / theta_i per pass) is small
+  // because the FP32 Lanczos ran to convergence at the rounding level.
+  // Rayleigh-Ritz on the filtered span removes the mixing among candidates.
+  // K_r = K/4, K/2, then K, at most 8 passes; target 8e-9 ||H|| (or tol if
+  // looser), under the 1e-8 ||H|| bar for returned residuals (the returned
+  // residuals are recomputed exactly, so the bar is met, not estimated).
+  refine_target = std::max(o.tol, 8e-9) * normH;
+  K_r = std::max<long long>(16, K / 4);
+  passes = 0;
+  return fp32 && rmax > refine_target;
+}
+
+// Vn <- the q Ritz vectors nearest the target (padding columns zero), and
+// the coefficients of this pass's filter P^{K_r}.
+template <class T>
+void Realization<T>::refine_prepare() {
+  hipStream_t st = ctx->stream;
+  tr0 = now_s();
+  if (!Vnb.p) {
+    Vnb.ensure(sizeof(double) * (size_t)n * ldr);
+    launch_fill(st, Vnb.as<double>(), (long long)n * ldr, 0.0);  // padding columns stay zero
+  }
+  int *didx = static_cast<int *>(ctx->buf("idx").ensure(sizeof(int) * (size_t)(P + 64) * 2));
+  const std::vector<int> near = nearest(Efin, std::vector<char>(Efin.size(), 1), q);
+  PF_HIP(hipMemcpyAsync(didx, near.data(), sizeof(int) * q, hipMemcpyHostToDevice, st));
+  launch_gather_cols(st, n, q, WRb.as<double>(), ldr, didx, Vnb.as<double>(), ldr);
+  cheb_coeffs(sigma, K_r, coef_r, D_r);
+}
+
+// UR <- P^{K_r}(H~) Vn with the single-chain FP64 filter, in whole
+// 64-column launches and the power-of-two remainder.
+template <class T>
+void Realization<T>::refine_filter_single() {
+  double *cheb64 =
+      static_cast<double *>(ctx->buf("cheb64").ensure(sizeof(double) * 3 * (size_t)n * 64));
+  for (int c0 = 0; c0 < qpad; c0 += 64) {
+    const int w = std::min(64, qpad - c0);  // 64, or the power-of-two remainder
+    run_filter<double>(ctx, c, dt64b.as<double>(), a, w, Vnb.as<double>() + c0, ldr,
+                       URb.as<double>() + c0, ldr, K_r, coef_r, D_r, cheb64, false, &refine_bytes,
+                       false);
+  }
+}
+
+// After the pass's filter: SVQB orthonormalisation of UR, Rayleigh-Ritz,
+// and the stall check.  Returns whether another pass is wanted.
+template <class T>
+bool Realization<T>::refine_finish() {
+  hipStream_t st = ctx->stream;
+  DevBuf &partials = ctx->buf("partials");
+  DevBuf &eigwork = ctx->buf("eigwork");
+  double *UR = URb.as<double>(), *WR = WRb.as<double>();
+  double *Gr = static_cast<double *>(ctx->buf("Gr").ensure(sizeof(double) * (size_t)ldr * ldr * 3 + 16));
+  double *Yr = Gr + (size_t)ldr * ldr;
+  double *Mr = Yr + (size_t)ldr * ldr;
+  double *epsd = static_cast<double *>(ctx->buf("epsd").ensure(sizeof(double) * (size_t)ldr));
+  rr_apps += (double)(K_r + 1) * q;
+  // SVQB orthonormalisation of UR[:, :q] (twice): UR <- UR W Lambda^{-1/2}
+  for (int it = 0; it < 2; ++it) {
+    launch_gram(st, n, q, q, UR, ldr, UR, ldr, Gr, q, partials, ctx->num_cu);
+    launch_symmetrize(st, q, Gr, q);
+    sym_eig(st, q, Gr, epsd, Yr, eigwork);
+    std::vector<double> lam(q), W((size_t)q * q);
+    PF_HIP(hipMemcpyAsync(lam.data(), epsd, sizeof(double) * q, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipMemcpyAsync(W.data(), Yr, sizeof(double) * q * q, hipMemcpyDeviceToHost, st));
+    PF_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < q; ++i) {
+      const double f = (lam[i] > 1e-28 * lam[q - 1]) ? 1.0 / std::sqrt(lam[i]) : 0.0;
+      for (int k = 0; k < q; ++k) W[(size_t)k * q + i] *= f;
+    }
+    PF_HIP(hipMemcpyAsync(Mr, W.data(), sizeof(double) * q * q, hipMemcpyHostToDevice, st));
+    for (int c0 = 0; c0 < q; c0 += 64) {
+      const int w = std::min(64, q - c0);
+      launch_update(st, n, q, w, 1.0, UR, ldr, Mr + c0, q, 0.0, WR + c0, ldr);
+    }
+    PF_HIP(hipMemcpy2DAsync(UR, sizeof(double) * ldr, WR, sizeof(double) * ldr,
+                            sizeof(double) * q, n, hipMemcpyDeviceToDevice, st));
+  }
+  PF_HIP(hipStreamSynchronize(st));
+  t_refine += now_s() - tr0;
+  ++passes;
+  const double rprev = rmax;
+  rmax = rayleigh_ritz(q);
+  if (std::getenv("POLFED_VERBOSE"))
+    fprintf(stderr, "[polfed] refine pass %d: K_r %lld, %d vectors, max resid / ||H|| = %.3e\n",
+            passes, K_r, q, rmax / normH);
+  // a pass at (about) the full order K that gains less than 10% has
+  // stalled (a wanted direction missing from, or barely separated
+  // within, the refined span); more passes would not reach the target,
+  // and the caller's FP64 re-solve is cheaper than running them out
+  if (2 * K_r > K && rmax > 0.9 * rprev) return false;
+  K_r = std::min<long long>(2 * K_r, K);
+  return rmax > refine_target && passes < 8;
+}
+
+template <class T>
+int Realization<T>::fin_end(double *evals, double *evecs, double *resid, polfed_info *info) {
+  hipStream_t st = ctx->stream;
   if (evecs) {
     double *cm = static_cast<double *>(ctx->buf("colmajor").ensure(sizeof(double) * (size_t)n * nout));
-    launch_to_colmajor(st, n, nout, Vout, ldo, cm);
+    launch_to_colmajor(st, n, nout, Voutb.as<double>(), ldo, cm);
     PF_HIP(hipMemcpyAsync(evecs, cm, sizeof(double) * (size_t)n * nout, hipMemcpyDeviceToHost, st));
   }
   PF_HIP(hipStreamSynchronize(st));
-  double t_rr = now_s() - t3 - t_refine;
+  const double t_rr = now_s() - t3 - t_refine;
   filter_gpu_s += ctx->filter_gpu_s - ctx_gpu0;
   filter_launches += ctx->filter_launches - ctx_launch0;
 
   for (int i = 0; i < nout; ++i) {
     evals[i] = Esel[i];
-    resid[i] = r[i];
+    resid[i] = rres[i];
   }
   for (int i = nout; i < nev; ++i) {
     evals[i] = NAN;
     resid[i] = NAN;
   }
   int n_ok = 0;
-  double rmax = 0.0;
+  double rm = 0.0;
   for (int i = 0; i < nout; ++i) {
     // FP32 mode is held to the FP32 residual bar (its refinement target)
-    if (r[i] <= (fp32 ? std::max(o.tol, kFp32ResidBar) : o.tol) * normH) ++n_ok;
-    rmax = std::max(rmax, r[i]);
+    if (rres[i] <= (fp32 ? std::max(o.tol, kFp32ResidBar) : o.tol) * normH) ++n_ok;
+    rm = std::max(rm, rres[i]);
   }
+  polfed_info inf;
+  std::memset(&inf, 0, sizeof(inf));
+  inf.t_bounds = t_bounds;
   inf.E0 = E0;
   inf.E1 = E1;
   inf.E0w = E0w;
@@ -1210,24 +1278,41 @@ int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed
   inf.n_conv = n_ok;
   inf.refine_passes = passes;
   inf.t_refine = t_refine;
-  inf.max_resid = rmax;
+  inf.max_resid = rm;
   inf.t_filter = t_filter;
   inf.t_orth = t_orth;
   inf.t_eig = t_eig;
   inf.t_rr = t_rr;
   inf.t_total = now_s() - t_start;
-  inf.hv_apps = (double)(K + 1) * ms + rr_apps + o.bounds_steps;
+  inf.hv_apps = (double)(K + 1) * (m_done * s) + rr_apps + o.bounds_steps;
   inf.filter_bytes = bytes + refine_bytes;
   inf.filter_gpu_s = filter_gpu_s;
   inf.filter_launches = filter_launches;
   if (info) *info = inf;
+  // the refinement's device state is no longer needed
+  URb.release();
+  WRb.release();
+  Vnb.release();
+  Voutb.release();
+  dt64b.release();
   // OK only when every returned pair meets the accuracy bar: a run can stop
   // with N_ev converged Ritz pairs and still select an unconverged one as
   // one of the N_ev nearest (its residual then shows it)
   bool all_ok = nout == nev;
   for (int i = 0; i < nout; ++i)
-    if (!(r[i] <= std::max(o.tol, kFp32ResidBar) * normH)) all_ok = false;
-  return (converged && all_ok) ? POLFED_OK : POLFED_NOT_CONVERGED;
+    if (!(rres[i] <= std::max(o.tol, kFp32ResidBar) * normH)) all_ok = false;
+  return (converged_fin && all_ok) ? POLFED_OK : POLFED_NOT_CONVERGED;
+}
+
+template <class T>
+int Realization<T>::finalize(double *evals, double *evecs, double *resid, polfed_info *info) {
+  if (fin_begin()) {
+    do {
+      refine_prepare();
+      refine_filter_single();
+    } while (refine_finish());
+  }
+  return fin_end(evals, evecs, resid, info);
 }
 
 
@@ -1335,6 +1420,196 @@ int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opt
 // a HIP graph and replayed for every block.  Members whose order K_i is
 // below K_max idle for the first K_max - K_i steps; members that converged
 // are switched off in the device descriptor table.
+// Launch shape of the batched step kernel: the context's entry, else the
+// single-chain default with the tables as rank method and no column slices.
+static StepShape batch_shape_for(const polfed_ctx *ctx, int L, int S, bool fp32) {
+  auto it = ctx->batch_shapes.find(std::make_tuple(L, S, fp32 ? 4 : 8));
+  if (it != ctx->batch_shapes.end()) return it->second;
+  StepShape sh = default_shape(L, S, fp32);
+  sh.rank_incr = 0;
+  sh.xcd_slices = 1;
+  return sh;
+}
+
+// Algorithmic bytes of one realisation's batched Clenshaw filter (the byte
+// model of the single-chain filter: each streamed block once per step, the
+// state word and diagonal of every row where H~ is applied).
+template <class T>
+static double batched_filter_bytes(long long n, int S, long long K, const std::vector<double> &coef) {
+  double mv = 0.0;
+  for (long long jj = 0; jj < K; ++jj) {
+    const int streams = 1 + (jj >= 1) + (jj >= 2) + (coef[K - jj] != 0.0);
+    mv += (double)n * (S * (double)sizeof(T) * streams + (jj >= 1 ? 4.0 + sizeof(T) : 0.0));
+  }
+  mv += (double)n * (S * (double)sizeof(T) * (2 + (K >= 1) + (K >= 2)) +
+                     (K >= 1 ? 4.0 + sizeof(T) : 0.0));
+  return mv;
+}
+
+// Fill the chain fields and tile offsets of batch items (rows per tile rpi);
+// returns the launch's total tiles.
+template <class T>
+static long long fill_batch_chains(std::vector<BatchItem<T>> &items,
+                                   const std::vector<const Chain *> &chains, long long rpi) {
+  long long tiles = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const Chain &c = *chains[i];
+    const Basis &b = *c.basis;
+    BatchItem<T> &it = items[i];
+    it.states = b.states.as<uint32_t>();
+    it.tabA = b.tabA.as<int32_t>();
+    it.tabB = b.tabB.as<uint16_t>();
+    it.n = b.n;
+    it.L = c.L;
+    it.half = b.half;
+    it.lomask = (1u << b.half) - 1u;
+    it.fullmask = (c.L >= 32) ? 0xffffffffu : ((1u << c.L) - 1u);
+    it.tile0 = tiles;
+    tiles += (b.n + rpi - 1) / rpi;
+  }
+  return tiles;
+}
+
+// The distinct rank tables of a batched launch's chains, to be staged in
+// LDS (each item's tab set): at most kMaxBatchTables lengths, each L <=
+// kMaxLdsTableL, 96 KB in all; otherwise count = 0 and every realisation
+// reads its tables from global memory.
+template <class T>
+static BatchTables batch_tables(std::vector<BatchItem<T>> &items,
+                                const std::vector<const Chain *> &chains) {
+  BatchTables bt;
+  std::memset(&bt, 0, sizeof(bt));
+  std::map<const Basis *, int> idx;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const Basis *b = chains[i]->basis;
+    auto f = idx.find(b);
+    if (f == idx.end()) {
+      if (bt.count == kMaxBatchTables || chains[i]->L > kMaxLdsTableL) {
+        std::memset(&bt, 0, sizeof(bt));
+        return bt;
+      }
+      const int k = bt.count++;
+      bt.A[k] = b->tabA.as<int32_t>();
+      bt.B[k] = b->tabB.as<uint16_t>();
+      bt.half[k] = b->half;
+      bt.off[k] = bt.ints;
+      bt.ints += (1 << b->half) + (1 << b->half) / 2;
+      f = idx.emplace(b, k).first;
+    }
+    items[i].tab = f->second;
+  }
+  if ((size_t)bt.ints * sizeof(int32_t) > (size_t)96 * 1024) std::memset(&bt, 0, sizeof(bt));
+  return bt;
+}
+
+// The FP64 refinement filters UR = P^{K_r}(H~) Vn of the members `ids`
+// (after their refine_prepare), as batched Clenshaw launches: per 64-column
+// chunk of the refined block, the members with that chunk, in sub-batches
+// whose recurrence buffers stay within 4 GiB.  The kernel time is shared
+// among the members in proportion to their rows times steps.
+template <class T>
+static void refine_batched(polfed_ctx *ctx, std::vector<std::unique_ptr<Realization<T>>> &rs,
+                           const std::vector<int> &ids) {
+  hipStream_t st = ctx->stream;
+  std::map<std::pair<int, int>, std::vector<int>> chunks;  // (first column, width) -> members
+  for (int i : ids)
+    for (int c0 = 0; c0 < rs[i]->qpad; c0 += 64)
+      chunks[std::make_pair(c0, std::min(64, rs[i]->qpad - c0))].push_back(i);
+  hipEvent_t e0, e1;
+  PF_HIP(hipEventCreate(&e0));
+  PF_HIP(hipEventCreate(&e1));
+  try {
+    for (auto &ch : chunks) {
+      const int c0 = ch.first.first, w = ch.first.second;
+      const std::vector<int> &all = ch.second;
+      size_t k0 = 0;
+      while (k0 < all.size()) {
+        size_t k1 = k0, tot = 0;
+        while (k1 < all.size()) {
+          const size_t need = sizeof(double) * 3 * (size_t)rs[all[k1]]->n * w;
+          if (k1 > k0 && tot + need > ((size_t)4 << 30)) break;
+          tot += need;
+          ++k1;
+        }
+        const int B = (int)(k1 - k0);
+        double *cheb = static_cast<double *>(ctx->buf("ref_cheb").ensure(tot));
+        size_t ncoef = 0;
+        int Lmax = 0;
+        long long Kmax = 0;
+        for (size_t k = k0; k < k1; ++k) {
+          const Realization<T> &r = *rs[all[k]];
+          ncoef += r.coef_r.size();
+          Lmax = std::max(Lmax, r.c.L);
+          Kmax = std::max(Kmax, r.K_r);
+        }
+        double *coefs = static_cast<double *>(ctx->buf("ref_coef").ensure(sizeof(double) * ncoef));
+        std::vector<BatchItem<double>> items(B);
+        std::vector<const Chain *> chains(B);
+        size_t co = 0, bo = 0;
+        const Realization<T> *rmax_L = rs[all[k0]].get();
+        for (int k = 0; k < B; ++k) {
+          Realization<T> &r = *rs[all[k0 + k]];
+          if (r.c.L == Lmax) rmax_L = &r;
+          PF_HIP(hipMemcpyAsync(coefs + co, r.coef_r.data(), sizeof(double) * r.coef_r.size(),
+                                hipMemcpyHostToDevice, st));
+          BatchItem<double> &it = items[k];
+          std::memset(&it, 0, sizeof(it));
+          it.dt = r.dt64b.template as<double>();
+          it.X = r.Vnb.template as<double>() + c0;
+          it.ldx = r.ldr;
+          it.buf = cheb + bo;
+          it.Y = r.URb.template as<double>() + c0;
+          it.ldy = r.ldr;
+          it.coef = coefs + co;
+          it.Dinv = 1.0 / r.D_r;
+          it.w1 = r.a * r.c.J1;
+          it.w2 = r.a * r.c.J2;
+          it.K = r.K_r;
+          it.active = 1;
+          chains[k] = &r.c;
+          co += r.coef_r.size();
+          bo += (size_t)3 * r.n * w;
+        }
+        const StepShape shape = batch_shape_for(ctx, Lmax, w, false);
+        const long long total = fill_batch_chains(items, chains, batched_tile_rows<double>(w, shape));
+        const BatchTables bt = batch_tables(items, chains);
+        BatchItem<double> *itemsd = static_cast<BatchItem<double> *>(
+            ctx->buf("ref_items").ensure(sizeof(BatchItem<double>) * B));
+        PF_HIP(hipMemcpyAsync(itemsd, items.data(), sizeof(BatchItem<double>) * B,
+                              hipMemcpyHostToDevice, st));
+        StepArgs<double> base = base_args<double>(rmax_L->c, rmax_L->dt64b.template as<double>());
+        PF_HIP(hipEventRecord(e0, st));
+        for (long long j = 0; j <= Kmax; ++j)
+          launch_step_batched<double>(st, w, base, itemsd, B, j, Kmax, total, bt, shape,
+                                      ctx->num_cu);
+        PF_HIP(hipEventRecord(e1, st));
+        PF_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        PF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        double wsum = 0.0;
+        for (int k = 0; k < B; ++k) wsum += (double)items[k].n * (items[k].K + 1);
+        if (std::getenv("POLFED_VERBOSE"))
+          fprintf(stderr, "[polfed] batched refinement filter: %d members, width %d, K_max %lld: "
+                          "%.2f s\n", B, w, Kmax, 1e-3 * ms);
+        for (int k = 0; k < B; ++k) {
+          Realization<T> &r = *rs[all[k0 + k]];
+          const double f = (double)items[k].n * (items[k].K + 1) / wsum;
+          r.filter_gpu_s += 1e-3 * ms * f;
+          r.filter_launches += (double)(Kmax + 1) * f;
+          r.refine_bytes += batched_filter_bytes<double>(r.n, w, r.K_r, r.coef_r);
+        }
+        k0 = k1;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  PF_HIP(hipEventDestroy(e0));
+  PF_HIP(hipEventDestroy(e1));
+}
+
 template <class T>
 static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
                             const polfed_opts &o, int nev, double *evals, double *evecs,
@@ -1353,12 +1628,13 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
     validate_model(&models[r]);
     PF_REQUIRE(nev >= 1 && nev <= polfed_dim(models[r].L), "nev must be in [1, dim] for every model");
   }
-  // group by (L, block size, J2 != 0): the batched kernel takes the bond
-  // ranges of the group from one member, so a group must agree on them
-  std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+  // group by (block size, J2 != 0): a group's realisations share every
+  // batched launch whatever their L (each brings its own basis); the bond
+  // set of the launch (with or without J2) is common to the group
+  std::map<std::pair<int, int>, std::vector<int>> groups;
   for (int r = 0; r < R; ++r) {
     const int s = o.block_size ? o.block_size : block_for(ctx, models[r].L, nev, o.precision);
-    groups[std::make_tuple(models[r].L, s, models[r].J2 != 0.0 ? 1 : 0)].push_back(r);
+    groups[std::make_pair(s, models[r].J2 != 0.0 ? 1 : 0)].push_back(r);
   }
   int worst = POLFED_OK;
   // errors that belong to one realisation end that member only; the others
@@ -1372,7 +1648,7 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
     const double tg0 = now_s();
     std::vector<std::unique_ptr<Realization<T>>> rs(B);
     polfed_opts og = o;
-    og.block_size = std::get<1>(g.first);
+    og.block_size = g.first.first;
     long long Kmax = 0;
     int first_ok = -1;
     for (int i = 0; i < B; ++i) {
@@ -1393,37 +1669,52 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
       if (worst == POLFED_OK) worst = POLFED_NOT_CONVERGED;
       continue;
     }
-    const Realization<T> &r0 = *rs[first_ok];
-    const long long n = r0.n;
+    // the longest chain of the group names the launch shape
+    int rL = first_ok;
+    for (int i = 0; i < B; ++i)
+      if (!rs[i]->err && rs[i]->c.L > rs[rL]->c.L) rL = i;
+    const Realization<T> &r0 = *rs[rL];
     const int S = r0.s;
     // per-member recurrence buffers, coefficients and descriptors
+    size_t nbuf = 0, ncoef = 0;
+    for (auto &r : rs) {
+      nbuf += (size_t)3 * r->n * S;
+      ncoef += r->coef.size();
+    }
     DevBuf cheb, coefs, itemsd;
-    cheb.ensure(sizeof(T) * 3 * (size_t)n * S * B);
-    size_t ncoef = 0;
-    for (auto &r : rs) ncoef += r->coef.size();
+    cheb.ensure(sizeof(T) * nbuf);
     coefs.ensure(sizeof(double) * ncoef);
     std::vector<BatchItem<T>> items(B);
-    size_t co = 0;
+    std::vector<const Chain *> chains(B);
+    size_t co = 0, bo = 0;
     for (int i = 0; i < B; ++i) {
       Realization<T> &r = *rs[i];
       PF_HIP(hipMemcpyAsync(coefs.as<double>() + co, r.coef.data(), sizeof(double) * r.coef.size(),
                             hipMemcpyHostToDevice, st));
       BatchItem<T> &it = items[i];
+      std::memset(&it, 0, sizeof(it));
       it.dt = r.dt();
       it.X = r.Xs();
-      it.buf = cheb.as<T>() + (size_t)3 * n * S * i;
+      it.ldx = S;
+      it.buf = cheb.as<T>() + bo;
       it.Y = r.Ys();
+      it.ldy = S;
       it.coef = coefs.as<double>() + co;
       it.Dinv = 1.0 / r.D;
       it.w1 = (T)(r.a * r.c.J1);
       it.w2 = (T)(r.a * r.c.J2);
       it.K = r.K;
       it.active = r.err ? 0 : 1;
+      chains[i] = r.err ? &r0.c : &r.c;
+      if (r.err) it.K = 0;
       co += r.coef.size();
+      bo += (size_t)3 * r.n * S;
     }
+    const StepShape shape = batch_shape_for(ctx, r0.c.L, S, r0.fp32);
+    const long long total = fill_batch_chains(items, chains, batched_tile_rows<T>(S, shape));
+    const BatchTables bt = batch_tables(items, chains);
     itemsd.ensure(sizeof(BatchItem<T>) * B);
     StepArgs<T> base = base_args<T>(r0.c, r0.dt());
-    const StepShape shape = shape_for(ctx, r0.c.L, S, r0.fp32);
     hipGraphExec_t graph = nullptr;
     hipEvent_t e0, e1;
     PF_HIP(hipEventCreate(&e0));
@@ -1448,7 +1739,7 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
           try {
             for (long long j = 0; j <= Kmax; ++j)
               launch_step_batched<T>(ctx->own_stream, S, base, itemsd.as<BatchItem<T>>(), B, j, Kmax,
-                                     shape, ctx->num_cu);
+                                     total, bt, shape, ctx->num_cu);
           } catch (...) {
             hipGraph_t dummy = nullptr;
             (void)hipStreamEndCapture(ctx->own_stream, &dummy);
@@ -1466,8 +1757,8 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
           PF_HIP(hipGraphLaunch(graph, st));
         } else {
           for (long long j = 0; j <= Kmax; ++j)
-            launch_step_batched<T>(st, S, base, itemsd.as<BatchItem<T>>(), B, j, Kmax, shape,
-                                   ctx->num_cu);
+            launch_step_batched<T>(st, S, base, itemsd.as<BatchItem<T>>(), B, j, Kmax, total,
+                                   bt, shape, ctx->num_cu);
         }
         PF_HIP(hipEventRecord(e1, st));
         PF_HIP(hipEventSynchronize(e1));
@@ -1476,24 +1767,14 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
         gfilter += 1e-3 * ms;
         glaunch += (double)(Kmax + 1);
         // algorithmic bytes of the active members (same model as one filter)
-        for (int i = 0; i < B; ++i) {
-          if (!items[i].active) continue;
-          const long long K = rs[i]->K;
-          double mv = 0.0;
-          for (long long jj = 0; jj < K; ++jj) {
-            const int streams = 1 + (jj >= 1) + (jj >= 2) + (rs[i]->coef[K - jj] != 0.0);
-            mv += (double)n * (S * (double)sizeof(T) * streams + (jj >= 1 ? 4.0 + sizeof(T) : 0.0));
-          }
-          mv += (double)n * (S * (double)sizeof(T) * (2 + (K >= 1) + (K >= 2)) +
-                             (K >= 1 ? 4.0 + sizeof(T) : 0.0));
-          rs[i]->bytes += mv;
-        }
+        for (int i = 0; i < B; ++i)
+          if (items[i].active) rs[i]->bytes += batched_filter_bytes<T>(rs[i]->n, S, rs[i]->K, rs[i]->coef);
         const double tf = now_s() - tf0;
         for (int i = 0; i < B; ++i)
           if (items[i].active) rs[i]->t_filter += tf / nact;
         // every active member's block, then their convergence checks: the
-        // members advance in lock step, so the checks share one size and
-        // their eigenproblems run in one batched launch when small enough
+        // members due at one T_m size run their eigenproblems in one batched
+        // launch when small enough
         std::vector<int> due;
         for (int i = 0; i < B; ++i) {
           if (!items[i].active) continue;
@@ -1505,30 +1786,31 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
             rs[i]->done = true;
           }
         }
-        if (!due.empty()) {
-          const int msz = rs[due[0]]->check_size();
-          bool same = true;
-          for (int i : due) same = same && rs[i]->check_size() == msz;
+        std::map<int, std::vector<int>> by_size;
+        for (int i : due) by_size[rs[i]->check_size()].push_back(i);
+        for (auto &bs : by_size) {
+          const int msz = bs.first;
+          const std::vector<int> &dz = bs.second;
           bool batched = false;
-          if (same && due.size() > 1 && msz <= 128) {
+          if (dz.size() > 1 && msz <= 128) {
             const double te0 = now_s();
-            const size_t mm = (size_t)msz * msz, nd = due.size();
+            const size_t mm = (size_t)msz * msz, nd = dz.size();
             double *Aall = static_cast<double *>(ctx->buf("bat_eig").ensure(
                 sizeof(double) * (3 * mm + msz) * nd));
             double *V0all = Aall + mm * nd, *Vall = V0all + mm * nd, *wall = Vall + mm * nd;
-            for (size_t k = 0; k < nd; ++k) rs[due[k]]->check_prepare(Aall + k * mm, V0all + k * mm);
+            for (size_t k = 0; k < nd; ++k) rs[dz[k]]->check_prepare(Aall + k * mm, V0all + k * mm);
             batched = sym_eig_batched(st, msz, (int)nd, Aall, V0all, wall, Vall);
             if (batched) {
               PF_HIP(hipStreamSynchronize(st));
               const double share = (now_s() - te0) / nd;
               for (size_t k = 0; k < nd; ++k) {
-                rs[due[k]]->t_eig += share;
-                rs[due[k]]->check_finish(wall + k * msz, Vall + k * mm);
+                rs[dz[k]]->t_eig += share;
+                rs[dz[k]]->check_finish(wall + k * msz, Vall + k * mm);
               }
             }
           }
           if (!batched)
-            for (int i : due) rs[i]->check_single();
+            for (int i : dz) rs[i]->check_single();
         }
       }
     } catch (...) {
@@ -1540,7 +1822,37 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
     if (graph) PF_HIP(hipGraphExecDestroy(graph));
     PF_HIP(hipEventDestroy(e0));
     PF_HIP(hipEventDestroy(e1));
+    cheb.release();
     const double tg1 = now_s();
+    // Rayleigh-Ritz of every member, then the FP64 refinement passes of
+    // those that want them, each pass's filters batched
+    std::vector<int> ref;
+    for (int i = 0; i < B; ++i) {
+      if (rs[i]->err) continue;
+      rs[i]->filter_gpu_s = gfilter / B;
+      rs[i]->filter_launches = glaunch / B;
+      if (rs[i]->fin_begin()) ref.push_back(i);
+    }
+    const double tb1 = now_s();
+    double t_prep = 0.0, t_rfilt = 0.0, t_fin = 0.0;
+    while (!ref.empty()) {
+      const double ta = now_s();
+      for (int i : ref) rs[i]->refine_prepare();
+      const double tb = now_s();
+      refine_batched<T>(ctx, rs, ref);
+      const double tc = now_s();
+      std::vector<int> more;
+      for (int i : ref)
+        if (rs[i]->refine_finish()) more.push_back(i);
+      ref.swap(more);
+      t_prep += tb - ta;
+      t_rfilt += tc - tb;
+      t_fin += now_s() - tc;
+    }
+    if (std::getenv("POLFED_VERBOSE"))
+      fprintf(stderr, "[polfed] batch finalize: Rayleigh-Ritz %.2f s, refinement prepare %.2f s, "
+                      "filters %.2f s, orthonormalisation and Rayleigh-Ritz %.2f s\n",
+              tb1 - tg1, t_prep, t_rfilt, t_fin);
     // members whose window was too narrow, and members whose FP32 result
     // misses the bar, each with its first attempt
     std::vector<int> widen, redo;
@@ -1553,11 +1865,9 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
         if (worst == POLFED_OK) worst = POLFED_NOT_CONVERGED;
         continue;
       }
-      rs[i]->filter_gpu_s = gfilter / B;
-      rs[i]->filter_launches = glaunch / B;
       polfed_info ir;
-      int rc = rs[i]->finalize(evals + (size_t)r * nev, evecs ? evecs + voff[r] : nullptr,
-                               resid + (size_t)r * nev, &ir);
+      int rc = rs[i]->fin_end(evals + (size_t)r * nev, evecs ? evecs + voff[r] : nullptr,
+                              resid + (size_t)r * nev, &ir);
       if (rs[i]->window_short()) {
         if (can_widen) {
           widen.push_back(r);
@@ -1574,6 +1884,9 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
       status[r] = rc;
       if (rc > 0 && worst == POLFED_OK) worst = rc;
     }
+    std::set<int> Ls;
+    for (auto &r : rs)
+      if (!r->err) Ls.insert(r->c.L);
     rs.clear();  // the group's device state is no longer needed
     // a sub-batch of the members `ids` with options `os` (in FP64 when
     // fp64); results go to their places, each info merged with the member's
@@ -1628,11 +1941,14 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
       rerun(redo, first, o64, true, merge_resolve_info);
     }
 
-    if (std::getenv("POLFED_VERBOSE"))
+    if (std::getenv("POLFED_VERBOSE")) {
+      std::string ls;
+      for (int L : Ls) ls += (ls.empty() ? "" : ",") + std::to_string(L);
       fprintf(stderr,
-              "[polfed] batch group L=%d s=%d: %d members, Lanczos %.2f s (filter kernels "
+              "[polfed] batch group L=%s s=%d: %d members, Lanczos %.2f s (filter kernels "
               "%.2f s), finalize %.2f s\n",
-              std::get<0>(g.first), std::get<1>(g.first), B, tg1 - tg0, gfilter, now_s() - tg1);
+              ls.c_str(), g.first.first, B, tg1 - tg0, gfilter, now_s() - tg1);
+    }
   }
   return worst;
 }

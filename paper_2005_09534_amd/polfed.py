@@ -104,6 +104,9 @@ def _load():
         "polfed_set_step_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int,
                                           c_int, c_int, c_int, c_int]),
         "polfed_get_step_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 7),
+        "polfed_set_batch_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int,
+                                           c_int, c_int]),
+        "polfed_get_batch_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 5),
         "polfed_set_graphs": (c_int, [c_void_p, c_int]),
         "polfed_set_filter_form": (c_int, [c_void_p, c_int]),
         "polfed_set_block_size": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
@@ -363,6 +366,19 @@ class Context:
                                               int(lds_tables), int(early_loads),
                                               int(rank_incremental), int(xcd_slices)),
                     "set_step_shape")
+
+    def set_batch_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1,
+                        early_loads=0):
+        self._check(LIB.polfed_set_batch_shape(self.h, L, nvec, precision, threads, lpl,
+                                               wg_per_cu, lds_tables, early_loads),
+                    "set_batch_shape")
+
+    def get_batch_shape(self, L, nvec, precision):
+        """(threads, lpl, wg_per_cu, lds_tables, early_loads) of the batched kernel."""
+        out = [c_int() for _ in range(5)]
+        self._check(LIB.polfed_get_batch_shape(self.h, L, nvec, precision,
+                                               *[ctypes.byref(o) for o in out]), "get_batch_shape")
+        return tuple(o.value for o in out)
 
     def get_step_shape(self, L, nvec, precision):
         """(threads, lpl, wg_per_cu, lds_tables, early_loads, rank_incremental, xcd_slices)."""

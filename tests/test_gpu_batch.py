@@ -203,3 +203,27 @@ def test_batch_member_error_leaves_the_others(ctx, pf):
     Ed = w[dense.nearest_from_spectrum(w, sigma, 6)]
     for i in (0, 2):
         assert np.abs(res["E"][i] - Ed).max() <= 1e-10 * normH
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mixed_length_launch_equals_separate_batches(ctx, pf, precision):
+    """Realisations of different L with one block size share every batched
+    launch (each brings its own basis; tile ranges per realisation): the
+    mixed batch returns what the per-L batches return (eigenvalues within
+    1e-10 ||H||, same K), and FP32 members go through the batched FP64
+    refinement in both."""
+    chains = _members(12, Ls=(10, 12, 14, 16))
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in chains]
+    nev, s = 8, 4
+    mixed = ctx.solve_batch(models, nev, vectors=False, block_size=s, precision=precision)
+    assert all(st == pf.OK for st in mixed["status"]), mixed["status"]
+    for L in (10, 12, 14, 16):
+        idx = [i for i, c in enumerate(chains) if c.L == L]
+        sep = ctx.solve_batch([models[i] for i in idx], nev, vectors=False, block_size=s,
+                              precision=precision)
+        for k, i in enumerate(idx):
+            normH = mixed["info"][i]["normH"]
+            assert np.abs(sep["E"][k] - mixed["E"][i]).max() <= 1e-10 * normH, (L, i)
+            assert sep["info"][k]["K"] == mixed["info"][i]["K"]
+    if precision == 1:
+        assert max(i["refine_passes"] for i in mixed["info"]) >= 1
