@@ -48,7 +48,9 @@ enum polfed_status {
   POLFED_ENOMEM = -2,       /* device allocation failed                  */
   POLFED_EDEVICE = -3,      /* HIP runtime error                         */
   POLFED_EBOUNDS = -4,      /* spectral bounds too tight: filter blew up
-                               (checked on every Lanczos block)           */
+                               (checked on every Lanczos block; the solve
+                               calls retry with the margin eta doubled,
+                               three times, before returning it)          */
   POLFED_EBREAKDOWN = -5    /* Lanczos block could not be refilled       */
 };
 

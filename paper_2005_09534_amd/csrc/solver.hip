@@ -541,6 +541,8 @@ constexpr double kMaxWindowFactor = 12.0;
 // relative to the FP64 filter, measured at about 3.5 eps32 sqrt(K) with
 // eps32 = 2^-24, stays below 1e-4 up to K ~ 2.3e5; 2e5 keeps a margin.
 constexpr long long kFp32MaxOrder = 200000;
+// Retries with the bounds margin eta doubled after a filter left [-1, 1].
+constexpr int kBoundsRetries = 3;
 
 template <class T>
 struct Realization {
@@ -1394,32 +1396,43 @@ int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opt
   polfed_info inf;
   std::memset(&inf, 0, sizeof(inf));
   int rc;
-  if (o.precision == 1) {
-    rc = solve_widened<float>(ctx, model, o, nev, evals, evecs, resid, &inf);
-    if (inf.max_resid > kFp32ResidBar * inf.normH) {
-      // the FP32 result misses the bar: recompute with the FP64 filter
-      polfed_opts o64 = o;
-      o64.precision = 0;
-      polfed_info i64;
-      std::memset(&i64, 0, sizeof(i64));
-      rc = solve_widened<double>(ctx, model, o64, nev, evals, evecs, resid, &i64);
-      merge_resolve_info(i64, inf);
-      inf = i64;
+  // a filter that left [-1, 1] (the widened Lanczos bounds still missed part
+  // of the spectrum) ends the attempt with POLFED_EBOUNDS: the bounds margin
+  // eta is doubled and the solve repeated, three times at most
+  for (int attempt = 0;; ++attempt) {
+    try {
+      if (o.precision == 1) {
+        rc = solve_widened<float>(ctx, model, o, nev, evals, evecs, resid, &inf);
+        if (inf.max_resid > kFp32ResidBar * inf.normH) {
+          // the FP32 result misses the bar: recompute with the FP64 filter
+          polfed_opts o64 = o;
+          o64.precision = 0;
+          polfed_info i64;
+          std::memset(&i64, 0, sizeof(i64));
+          rc = solve_widened<double>(ctx, model, o64, nev, evals, evecs, resid, &i64);
+          merge_resolve_info(i64, inf);
+          inf = i64;
+        }
+      } else {
+        rc = solve_widened<double>(ctx, model, o, nev, evals, evecs, resid, &inf);
+      }
+      break;
+    } catch (const Error &e) {
+      if (e.code != POLFED_EBOUNDS || attempt == kBoundsRetries) throw;
+      o.eta *= 2.0;
     }
-  } else {
-    rc = solve_widened<double>(ctx, model, o, nev, evals, evecs, resid, &inf);
   }
   if (info) *info = inf;
   return rc;
 }
 
-// Batched solve: realisations are grouped by chain length (and block size);
-// each group advances in lock step, one Lanczos block at a time, with the
-// filter of all its active members in one persistent launch per Chebyshev
-// step (k_step_batched), the K_max + 1 launches of a block captured once in
-// a HIP graph and replayed for every block.  Members whose order K_i is
-// below K_max idle for the first K_max - K_i steps; members that converged
-// are switched off in the device descriptor table.
+// Batched solve: realisations are grouped by block size and J2 != 0 (chain
+// lengths may mix); each group advances in lock step, one Lanczos block at a
+// time, with the filter of all its active members in one persistent launch
+// per Chebyshev step (k_step_batched), the K_max + 1 launches of a block
+// captured once in a HIP graph and replayed for every block.  Members whose
+// order K_i is below K_max idle for the first K_max - K_i steps; members
+// that converged are switched off in the device descriptor table.
 // Launch shape of the batched step kernel: the context's entry, else the
 // single-chain default with the tables as rank method and no column slices.
 static StepShape batch_shape_for(const polfed_ctx *ctx, int L, int S, bool fp32) {
@@ -1966,9 +1979,52 @@ int solve_batch(polfed_ctx *ctx, int R, const polfed_model *models, const polfed
     ~FormGuard() { c->filter_form = saved; }
   } guard{ctx, ctx->filter_form};
   ctx->filter_form = POLFED_FORM_CLENSHAW;
-  if (o.precision == 1)
-    return solve_batch_impl<float>(ctx, R, models, o, nev, evals, evecs, resid, infos, status);
-  return solve_batch_impl<double>(ctx, R, models, o, nev, evals, evecs, resid, infos, status);
+  auto run = [&](int n, const polfed_model *ms, const polfed_opts &oo, double *ev, double *vv,
+                 double *rs, polfed_info *inf, int *st) {
+    return oo.precision == 1 ? solve_batch_impl<float>(ctx, n, ms, oo, nev, ev, vv, rs, inf, st)
+                             : solve_batch_impl<double>(ctx, n, ms, oo, nev, ev, vv, rs, inf, st);
+  };
+  int worst = run(R, models, o, evals, evecs, resid, infos, status);
+  // members whose filter left [-1, 1] (POLFED_EBOUNDS): again as a batch of
+  // their own with the bounds margin eta doubled, three times at most
+  for (int attempt = 0; attempt < kBoundsRetries; ++attempt) {
+    std::vector<int> ids;
+    for (int r = 0; r < R; ++r)
+      if (status[r] == POLFED_EBOUNDS) ids.push_back(r);
+    if (ids.empty()) break;
+    o.eta *= 2.0;
+    std::vector<size_t> voff(R + 1, 0);
+    for (int r = 0; r < R; ++r) voff[r + 1] = voff[r] + (size_t)polfed_dim(models[r].L) * nev;
+    const int nr = (int)ids.size();
+    std::vector<polfed_model> sub(nr);
+    size_t tot = 0;
+    for (int k = 0; k < nr; ++k) {
+      sub[k] = models[ids[k]];
+      tot += (size_t)polfed_dim(sub[k].L) * nev;
+    }
+    std::vector<double> ev((size_t)nr * nev), rs((size_t)nr * nev), vv(evecs ? tot : 0);
+    std::vector<polfed_info> inf(nr);
+    std::vector<int> st(nr);
+    run(nr, sub.data(), o, ev.data(), evecs ? vv.data() : nullptr, rs.data(), inf.data(),
+        st.data());
+    size_t off = 0;
+    for (int k = 0; k < nr; ++k) {
+      const int r = ids[k];
+      const size_t len = (size_t)polfed_dim(sub[k].L) * nev;
+      status[r] = st[k];
+      if (st[k] >= 0) {  // outputs of a member that failed again stay untouched
+        std::memcpy(evals + (size_t)r * nev, ev.data() + (size_t)k * nev, sizeof(double) * nev);
+        std::memcpy(resid + (size_t)r * nev, rs.data() + (size_t)k * nev, sizeof(double) * nev);
+        if (evecs) std::memcpy(evecs + voff[r], vv.data() + off, sizeof(double) * len);
+        if (infos) infos[r] = inf[k];
+      }
+      off += len;
+    }
+    worst = POLFED_OK;
+    for (int r = 0; r < R; ++r)
+      if (status[r] != POLFED_OK) worst = POLFED_NOT_CONVERGED;
+  }
+  return worst;
 }
 
 // ------------------------------------------------- stage-call helpers --

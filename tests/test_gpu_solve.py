@@ -262,9 +262,9 @@ def test_wide_window_returns_the_nearest(ctx, pf):
     the N_ev nearest (residual 4e-3, returned with status OK).  For wider
     windows the N_ev largest theta must now be the converged ones, and the
     status is OK only when every returned residual meets max(tol, 1e-8)
-    ||H||: the wide and the default window give the same answer, which the
-    FP32-filter path confirms (and which was checked once against the full
-    spectrum: exact to 3e-16 ||H||)."""
+    ||H||: the wide and the default window give the same answer, the 20
+    eigenvalues nearest the target by the oracle's shift-invert solve, and
+    the FP32-filter path agrees."""
     c = workloads.chain(16, 4.0, 1235)
     m = pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h)
     H = chain.hamiltonian_csr(c.L, c.J1, c.J2, c.Delta, c.h)
@@ -272,12 +272,15 @@ def test_wide_window_returns_the_nearest(ctx, pf):
     for wf in (6.0, 0.0):
         r = ctx.solve(m, 20, block_size=4, precision=0, window_factor=wf, vectors=True)
         normH = r["info"]["normH"]
+        sigma_H = r["info"]["sigma_energy"]
         res = np.linalg.norm(H @ r["V"] - r["V"] * r["E"], axis=0)
         np.testing.assert_allclose(res, r["resid"], rtol=1e-6, atol=1e-12 * normH)
         assert r["status"] == pf.OK, wf
         assert r["resid"].max() <= 1e-8 * normH, wf
         out[wf] = r["E"]
     assert np.abs(out[6.0] - out[0.0]).max() <= 1e-10 * normH
+    Ed, _ = dense.nearest_shift_invert(H, sigma_H, 20)
+    assert np.abs(out[0.0] - np.sort(Ed)).max() <= 1e-10 * normH
     r32 = ctx.solve(m, 20, block_size=4, precision=1, vectors=False)
     assert r32["status"] == pf.OK
     assert np.abs(out[0.0] - r32["E"]).max() <= 1e-10 * normH
