@@ -309,16 +309,18 @@ int polfed_get_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *
 /* Launch shape of the batched step kernel of polfed_solve_batch (its
  * Lanczos filters and FP64 refinement filters) for a launch whose longest
  * chain has length L, at block width nvec and precision: threads, loads per
- * lane, workgroups per CU, LDS tables and early loads as in
- * polfed_set_step_shape (the batched kernel always ranks with the tables and
- * takes no column slices; the tables go to LDS only when every chain of the
- * launch has length L).  Separate from the single-chain shape: a batched
- * launch walks many chains, where the best shape differs.  Without an entry
- * the built-in single-chain default is used. */
+ * lane, workgroups per CU, LDS tables, early loads and column slices as in
+ * polfed_set_step_shape (the batched kernel always ranks with the tables;
+ * the tables of every chain length in a launch go to LDS together).
+ * Separate from the single-chain shape: a batched launch walks many chains,
+ * where the best shape differs.  Without an entry a built-in default is
+ * used (the single-chain default without column slices). */
 int polfed_set_batch_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads,
-                           int lpl, int wg_per_cu, int lds_tables, int early_loads);
+                           int lpl, int wg_per_cu, int lds_tables, int early_loads,
+                           int xcd_slices);
 int polfed_get_batch_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads,
-                           int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads);
+                           int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads,
+                           int *xcd_slices);
 /* Block size used when opts->block_size is 0 for chains of length L at the
  * given precision and N_ev (the autotuner's choice); without an entry a
  * built-in rule is used (about N_ev/4, capped at 16 in FP64 and 32 in FP32,

@@ -446,7 +446,7 @@ int polfed_set_step_shape(polfed_ctx *ctx, int L, int nvec, int precision, int t
 }
 
 int polfed_set_batch_shape(polfed_ctx *ctx, int L, int nvec, int precision, int threads, int lpl,
-                           int wg_per_cu, int lds_tables, int early_loads) {
+                           int wg_per_cu, int lds_tables, int early_loads, int xcd_slices) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
     PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
@@ -455,6 +455,9 @@ int polfed_set_batch_shape(polfed_ctx *ctx, int L, int nvec, int precision, int 
                "threads must be 256, 512 or 1024");
     PF_REQUIRE(lpl == 1 || lpl == 2 || lpl == 4, "lpl must be 1, 2 or 4");
     PF_REQUIRE(wg_per_cu >= 1 && wg_per_cu <= 32, "wg_per_cu must be in [1, 32]");
+    PF_REQUIRE((xcd_slices == 1 || xcd_slices == 2 || xcd_slices == 4 || xcd_slices == 8) &&
+                   xcd_slices <= nvec,
+               "xcd_slices must be 1, 2, 4 or 8 and at most nvec");
     StepShape sh;
     sh.threads = threads;
     sh.lpl = lpl;
@@ -462,26 +465,29 @@ int polfed_set_batch_shape(polfed_ctx *ctx, int L, int nvec, int precision, int 
     sh.lds_tables = lds_tables ? 1 : 0;
     sh.early_loads = early_loads ? 1 : 0;
     sh.rank_incr = 0;
-    sh.xcd_slices = 1;
+    sh.xcd_slices = xcd_slices;
     ctx->batch_shapes[std::make_tuple(L, nvec, precision ? 4 : 8)] = sh;
     return POLFED_OK;
   });
 }
 
 int polfed_get_batch_shape(polfed_ctx *ctx, int L, int nvec, int precision, int *threads,
-                           int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads) {
+                           int *lpl, int *wg_per_cu, int *lds_tables, int *early_loads,
+                           int *xcd_slices) {
   return guarded(ctx, [&] {
     PF_REQUIRE(polfed_dim(L) > 0 && L >= 4, "L must be even in [4, 30]");
     PF_REQUIRE(pow2_block(nvec), "nvec must be a power of two in [1, 64]");
     PF_REQUIRE(precision == 0 || precision == 1, "precision must be 0 or 1");
-    PF_REQUIRE(threads && lpl && wg_per_cu && lds_tables && early_loads, "NULL output");
+    PF_REQUIRE(threads && lpl && wg_per_cu && lds_tables && early_loads && xcd_slices,
+               "NULL output");
     StepShape sh;
     auto it = ctx->batch_shapes.find(std::make_tuple(L, nvec, precision ? 4 : 8));
     if (it != ctx->batch_shapes.end()) {
       sh = it->second;
     } else {
-      sh = default_shape(L, nvec, precision == 1);
+      sh = default_batch_shape(L, nvec, precision == 1);
     }
+    *xcd_slices = sh.xcd_slices;
     *threads = sh.threads;
     *lpl = sh.lpl;
     *wg_per_cu = sh.wg_per_cu;

@@ -371,7 +371,8 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
   const long long rows_per_iter = (long long)(blockDim.x >> 6) * RPW;
   long long t_begin, t_end, t_step;
   int slice;
-  xcd_tiles(ntiles, 1, slice, t_begin, t_end, t_step);
+  const int ns = base.nslices;  // column slices: S is one slice's width
+  xcd_tiles(ntiles, ns, slice, t_begin, t_end, t_step);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int slot = lane / G;
@@ -400,8 +401,12 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
     a.lomask = it.lomask;
     a.fullmask = it.fullmask;
     a.dt = it.dt;
-    const size_t blk = (size_t)it.n * S;
-    T *bufs[3] = {it.buf, it.buf + blk, it.buf + 2 * blk};
+    // recurrence buffers: three blocks of n x (ns S), each slice-major (this
+    // group's slice: n x S at slice n S); X and Y row-major, this slice's
+    // columns at offset slice S
+    const size_t blk = (size_t)it.n * S * ns;
+    const size_t soff = (size_t)slice * it.n * S;
+    T *bufs[3] = {it.buf + soff, it.buf + blk + soff, it.buf + 2 * blk + soff};
     a.ldv = a.ldw = S;
     a.ldx = it.ldx;
     if (j < Kmax) {
@@ -411,16 +416,16 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
       a.V = (ji >= 1) ? bufs[(ji - 1) % 3] : nullptr;
       a.W = (ji >= 2) ? bufs[(ji - 2) % 3] : nullptr;
       const double ck = it.coef[k];
-      a.X = (ck != 0.0) ? it.X : nullptr;
+      a.X = (ck != 0.0) ? it.X + (size_t)slice * S : nullptr;
       a.alpha = (T)ck;
       a.dscale = T(2);
       a.w1 = it.w1;
       a.w2 = it.w2;
       a.gamma = T(-1);
     } else {
-      a.out = it.Y;
+      a.out = it.Y + (size_t)slice * S;
       a.ldo = it.ldy;
-      a.X = it.X;
+      a.X = it.X + (size_t)slice * S;
       a.alpha = (T)(it.coef[0] * it.Dinv);
       a.V = (it.K >= 1) ? bufs[(it.K - 1) % 3] : nullptr;
       a.W = (it.K >= 2) ? bufs[(it.K - 2) % 3] : nullptr;
@@ -546,7 +551,7 @@ static void launch_batched_s(hipStream_t st, const StepArgs<T> &a, const BatchIt
                              int B, long long j, long long Kmax, long long ntiles,
                              const BatchTables &bt, const StepShape &shape, int num_cu) {
   const int threads = shape.threads;
-  long long nwg = std::min((long long)num_cu * shape.wg_per_cu, ntiles);
+  long long nwg = std::min((long long)num_cu * shape.wg_per_cu, ntiles * a.nslices);
   nwg = ((nwg + 7) / 8) * 8;
   const bool lds = shape.lds_tables && bt.count > 0;
   const size_t shm = lds ? sizeof(int32_t) * (size_t)bt.ints : 0;
@@ -604,23 +609,30 @@ void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const Batc
   if (total_tiles <= 0 || B <= 0) return;
   if (shape.threads != 256 && shape.threads != 512 && shape.threads != 1024)
     throw Error(POLFED_EINVAL, "step kernel: threads must be 256, 512 or 1024");
+  const int ns = shape.xcd_slices;
+  if (ns != 1 && ns != 2 && ns != 4 && ns != 8)
+    throw Error(POLFED_EINVAL, "step kernel: column slices must be 1, 2, 4 or 8");
+  if (S % ns != 0) throw Error(POLFED_EINVAL, "step kernel: width not divisible by slices");
+  StepArgs<T> a0 = a;
+  a0.nslices = ns;
+  S /= ns;  // the kernel's template width is one slice
 #define PF_BATCH_CASE(SS)                                                                  \
   case SS: {                                                                               \
     constexpr int M = max_lpl<T, SS>();                                                    \
     const int lpl = std::min(shape.lpl, M);                                                \
     if constexpr (M >= 4)                                                                  \
       if (lpl == 4) {                                                                      \
-        launch_batched_s<T, SS, 4>(st, a, items, B, j, Kmax, total_tiles, tables, shape,   \
+        launch_batched_s<T, SS, 4>(st, a0, items, B, j, Kmax, total_tiles, tables, shape,   \
                                    num_cu);                                                \
         break;                                                                             \
       }                                                                                    \
     if constexpr (M >= 2)                                                                  \
       if (lpl == 2) {                                                                      \
-        launch_batched_s<T, SS, 2>(st, a, items, B, j, Kmax, total_tiles, tables, shape,   \
+        launch_batched_s<T, SS, 2>(st, a0, items, B, j, Kmax, total_tiles, tables, shape,   \
                                    num_cu);                                                \
         break;                                                                             \
       }                                                                                    \
-    launch_batched_s<T, SS, 1>(st, a, items, B, j, Kmax, total_tiles, tables, shape,       \
+    launch_batched_s<T, SS, 1>(st, a0, items, B, j, Kmax, total_tiles, tables, shape,       \
                                num_cu);                                                    \
     break;                                                                                 \
   }
@@ -638,9 +650,11 @@ void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const Batc
 }
 
 // Rows per tile of the batched kernel: the workgroup's waves times the rows
-// a wave covers at the loads per lane the launcher picks for this width.
+// a wave covers at the loads per lane the launcher picks for this width
+// (split into the shape's column slices).
 template <class T>
 long long batched_tile_rows(int S, const StepShape &shape) {
+  if (shape.xcd_slices > 1 && S % shape.xcd_slices == 0) S /= shape.xcd_slices;
   auto rows = [&](auto s_c) -> long long {
     constexpr int SS = decltype(s_c)::value;
     constexpr int M = max_lpl<T, SS>();

@@ -222,8 +222,10 @@ template <class T>
 void launch_step_batched(hipStream_t st, int S, const StepArgs<T> &a, const BatchItem<T> *items,
                          int B, long long j, long long Kmax, long long total_tiles,
                          const BatchTables &tables, const StepShape &shape, int num_cu);
-// Built-in default shape (used when the context holds no tuned entry).
+// Built-in default shapes (used when the context holds no tuned entry) of
+// the single-chain and the batched step kernel.
 StepShape default_shape(int L, int S, bool fp32);
+StepShape default_batch_shape(int L, int S, bool fp32);
 
 // out (slice-major: nslices blocks of n x (S / nslices), each row's slice
 // contiguous) <- X (n x S, row-major, leading dimension ldx).

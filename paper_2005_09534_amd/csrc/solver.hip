@@ -1438,10 +1438,7 @@ int solve_one(polfed_ctx *ctx, const polfed_model *model, const polfed_opts *opt
 static StepShape batch_shape_for(const polfed_ctx *ctx, int L, int S, bool fp32) {
   auto it = ctx->batch_shapes.find(std::make_tuple(L, S, fp32 ? 4 : 8));
   if (it != ctx->batch_shapes.end()) return it->second;
-  StepShape sh = default_shape(L, S, fp32);
-  sh.rank_incr = 0;
-  sh.xcd_slices = 1;
-  return sh;
+  return default_batch_shape(L, S, fp32);
 }
 
 // Algorithmic bytes of one realisation's batched Clenshaw filter (the byte
@@ -2095,6 +2092,18 @@ StepShape default_shape(int L, int S, bool fp32) {
     sh.xcd_slices = 2;
   }
   (void)S;
+  return sh;
+}
+
+StepShape default_batch_shape(int L, int S, bool fp32) {
+  // The single-chain default with the tables as rank method and no column
+  // slices.  (Four slices for the FP64 refinement filters of the 512-
+  // realisation batch, which would keep one L = 18 realisation's gathered
+  // slice in an XCD's L2, measured slower at 32 columns (64-byte slices of
+  // 128-byte lines: 7.9 against 6.4 s for one pass) and even at 64.)
+  StepShape sh = default_shape(L, S, fp32);
+  sh.rank_incr = 0;
+  sh.xcd_slices = 1;
   return sh;
 }
 

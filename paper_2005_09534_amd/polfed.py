@@ -105,8 +105,8 @@ def _load():
                                           c_int, c_int, c_int, c_int]),
         "polfed_get_step_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 7),
         "polfed_set_batch_shape": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int,
-                                           c_int, c_int]),
-        "polfed_get_batch_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 5),
+                                           c_int, c_int, c_int]),
+        "polfed_get_batch_shape": (c_int, [c_void_p, c_int, c_int, c_int] + [ctypes.POINTER(c_int)] * 6),
         "polfed_set_graphs": (c_int, [c_void_p, c_int]),
         "polfed_set_filter_form": (c_int, [c_void_p, c_int]),
         "polfed_set_block_size": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
@@ -368,14 +368,15 @@ class Context:
                     "set_step_shape")
 
     def set_batch_shape(self, L, nvec, precision, threads, lpl, wg_per_cu, lds_tables=1,
-                        early_loads=0):
+                        early_loads=0, xcd_slices=1):
         self._check(LIB.polfed_set_batch_shape(self.h, L, nvec, precision, threads, lpl,
-                                               wg_per_cu, lds_tables, early_loads),
+                                               wg_per_cu, lds_tables, early_loads, xcd_slices),
                     "set_batch_shape")
 
     def get_batch_shape(self, L, nvec, precision):
-        """(threads, lpl, wg_per_cu, lds_tables, early_loads) of the batched kernel."""
-        out = [c_int() for _ in range(5)]
+        """(threads, lpl, wg_per_cu, lds_tables, early_loads, xcd_slices) of the
+        batched kernel."""
+        out = [c_int() for _ in range(6)]
         self._check(LIB.polfed_get_batch_shape(self.h, L, nvec, precision,
                                                *[ctypes.byref(o) for o in out]), "get_batch_shape")
         return tuple(o.value for o in out)

@@ -227,3 +227,32 @@ def test_mixed_length_launch_equals_separate_batches(ctx, pf, precision):
             assert sep["info"][k]["K"] == mixed["info"][i]["K"]
     if precision == 1:
         assert max(i["refine_passes"] for i in mixed["info"]) >= 1
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_column_slices_bitwise(ctx, pf, precision):
+    """The batched kernel with its block split into XCD column slices (the
+    recurrence buffers slice-major) computes the same numbers as unsplit: a
+    batch at s = 32 (FP64 filter), and the FP64 refinement filters of an
+    FP32 batch (width 32 or 64), give identical eigenvalues with 1 and with
+    4 slices."""
+    chains = [workloads.chain(12, 2.0, 3100 + r) for r in range(3)]
+    models = [pf.make_model(c.L, c.J1, c.J2, c.Delta, c.h) for c in chains]
+    keys = [(12, 32, 0), (12, 64, 0)] if precision == 1 else [(12, 32, 0)]
+    saved = {k: ctx.get_batch_shape(*k) for k in keys}
+    out = {}
+    try:
+        for ns in (1, 4):
+            for k in keys:
+                sh = saved[k]
+                ctx.set_batch_shape(*k, *sh[:5], ns)
+            s = 8 if precision == 1 else 32
+            r = ctx.solve_batch(models, 40, vectors=False, block_size=s, precision=precision)
+            assert all(st == pf.OK for st in r["status"]), r["status"]
+            out[ns] = r
+    finally:
+        for k in keys:
+            ctx.set_batch_shape(*k, *saved[k])
+    assert np.array_equal(out[1]["E"], out[4]["E"])
+    if precision == 1:
+        assert max(i["refine_passes"] for i in out[4]["info"]) >= 1
