@@ -331,3 +331,64 @@ def test_filter_fp32_vs_fp64_at_the_l22_order(ctx, pf):
     assert np.abs(G - G.T).max() <= 1e-10 * np.abs(G).max()
     del X, Y64, Y32
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec,shape", [(0, (256, 2, 2, 1, 0, 0, 4)), (1, (512, 2, 2, 1, 0, 0, 2))])
+def test_filter_l26_bench_shape_sampled_rows(ctx, pf, prec, shape):
+    """The L = 26 chain (10,400,600 rows, 64 columns) through the filter in
+    the launch configuration the benchmark times (XCD column slices: four of
+    16 columns in FP64, two of 32 in FP32): Y = sum_k c_k T_k(H~) X / D at
+    K = 2, i.e. (c_0 X + c_1 H~X + c_2 (2 H~^2 X - X)) / D, on 100 sampled
+    rows against the oracle's per-row form of H (H~^2 X through the rows of
+    each sampled row's neighbours), coefficients from the oracle."""
+    c = workloads.c5().chains[0]
+    m = _model(pf, c)
+    L, n, s = 26, pf.dim(26), 64
+    E0w, E1w = -0.9 * L - 0.5 * float(np.abs(c.h).sum()), 0.8 * L + 0.5 * float(np.abs(c.h).sum())
+    a, b = chebyshev.rescale_coeffs(E0w, E1w)
+    sig = 0.013
+    K = 2
+    cc = chebyshev.cheb_coeffs(sig, K)
+    D = chebyshev.norm_D(sig, K)
+    saved = ctx.get_step_shape(L, s, prec)
+    g = torch.Generator(device="cuda").manual_seed(26)
+    X = torch.randn((n, s), generator=g, device="cuda", dtype=torch.float64)
+    if prec:
+        X = X.float()
+    try:
+        ctx.set_step_shape(L, s, prec, *shape)
+        Y = ctx.apply_filter(m, E0w, E1w, sig, K, X)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_step_shape(L, s, prec, *saved)
+    bas = chain.basis(L)
+    Xs = X.to(torch.float64)
+
+    def ht_row(state):  # {rank: H~ entry} of one row
+        ent = chain.hamiltonian_row(L, c.J1, c.J2, c.Delta, c.h, state)
+        cols = chain.rank(np.array(list(ent.keys()), dtype=np.uint32), bas)
+        vals = a * np.array(list(ent.values()))
+        r0 = int(chain.rank(np.array([state], dtype=np.uint32), bas)[0])
+        vals[list(cols).index(r0)] += b
+        return cols, vals
+
+    def htx(cols, vals):
+        return (torch.tensor(vals, device="cuda")[:, None] *
+                Xs[torch.from_numpy(cols.astype(np.int64)).cuda()]).sum(0)
+
+    rows = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(3).integers(0, n, 98)]))
+    worst = 0.0
+    for r in rows:
+        cols, vals = ht_row(bas[r])
+        h1 = htx(cols, vals)
+        h2 = torch.zeros(s, dtype=torch.float64, device="cuda")
+        for cj, vj in zip(cols, vals):
+            cj2, vj2 = ht_row(bas[cj])
+            h2 += vj * htx(cj2, vj2)
+        ref = (cc[0] * Xs[r] + cc[1] * h1 + cc[2] * (2.0 * h2 - Xs[r])) / D
+        err = float((Y[r].to(torch.float64) - ref).abs().max() / ref.abs().max())
+        worst = max(worst, err)
+    print(f"L=26 filter K=2, shape {shape}: worst sampled-row error {worst:.2e}")
+    assert worst <= (1e-5 if prec else 1e-12)
+    del X, Y, Xs
+    torch.cuda.empty_cache()
