@@ -285,7 +285,7 @@ __device__ __forceinline__ void stage_tables(const int32_t *gA, const uint16_t *
 // between XCDs), and the L2 holds more rows of the narrower slice.
 __device__ __forceinline__ void xcd_tiles(long long ntiles, int nslices, int &slice,
                                           long long &t_begin, long long &t_end,
-                                          long long &t_step) {
+                                          long long &t_step, bool interleave = false) {
   const unsigned nwg = gridDim.x;
   const unsigned b = blockIdx.x;
   slice = 0;
@@ -295,10 +295,19 @@ __device__ __forceinline__ void xcd_tiles(long long ntiles, int nslices, int &sl
     slice = x & (nslices - 1);
     const int parts = 8 / nslices;
     const int part = x / nslices;
-    const long long TX = (ntiles + parts - 1) / parts;
-    t_begin = (long long)part * TX + (long long)(b >> 3);
-    t_end = ((long long)part + 1) * TX < ntiles ? ((long long)part + 1) * TX : ntiles;
-    t_step = W;
+    if (interleave) {
+      // the parts take every parts-th tile, so all XCDs of a slice sweep one
+      // row window together (one window for the Infinity Cache to hold
+      // instead of `parts`)
+      t_begin = (long long)part + (long long)parts * (long long)(b >> 3);
+      t_end = ntiles;
+      t_step = (long long)parts * W;
+    } else {
+      const long long TX = (ntiles + parts - 1) / parts;
+      t_begin = (long long)part * TX + (long long)(b >> 3);
+      t_end = ((long long)part + 1) * TX < ntiles ? ((long long)part + 1) * TX : ntiles;
+      t_step = W;
+    }
   } else {  // (the launchers always round the grid to a multiple of 8)
     t_begin = b;
     t_end = ntiles;
@@ -319,7 +328,7 @@ __global__ __launch_bounds__(MAXT) void k_step(StepArgs<T> a) {
   const long long ntiles = (a.n + rows_per_iter - 1) / rows_per_iter;
   long long t_begin, t_end, t_step;
   int slice;
-  xcd_tiles(ntiles, a.nslices, slice, t_begin, t_end, t_step);
+  xcd_tiles(ntiles, a.nslices, slice, t_begin, t_end, t_step, a.interleave != 0);
   if (slice != 0) {  // this group's column slice of every operand
     if (a.X) a.X += slice * a.xss;
     if (a.V) a.V += slice * a.vss;
@@ -589,6 +598,9 @@ void launch_step(hipStream_t st, int S, const StepArgs<T> &a0, const StepShape &
   if (a.nslices != 1 && a.nslices != 2 && a.nslices != 4 && a.nslices != 8)
     throw Error(POLFED_EINVAL, "step kernel: column slices must be 1, 2, 4 or 8");
   if (S % a.nslices != 0) throw Error(POLFED_EINVAL, "step kernel: width not divisible by slices");
+  // blocks beyond the Infinity Cache (256 MB) are swept as one row window
+  // by all the XCDs of a slice; smaller ones keep a window per XCD
+  a.interleave = ((double)a.n * S * sizeof(T) > 256.0 * 1024.0 * 1024.0) ? 1 : 0;
   S /= a.nslices;  // the kernel's template width is one slice
   switch (S) {
     case 1: launch_step_lpl<T, 1>(st, a, shape, num_cu); break;

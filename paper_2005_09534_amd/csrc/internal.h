@@ -148,6 +148,10 @@ struct StepArgs {
   // leading dimension is then that of the slice.
   int nslices;
   long long xss, vss, wss, oss, accss, srcss;
+  // the parts of the rows an XCD group covers are interleaved tile by tile
+  // rather than contiguous (set by the launcher for blocks larger than the
+  // Infinity Cache)
+  int interleave;
   // stored neighbour pattern (rank mode 2): row r's neighbours are
   // csr_col[csr_ptr[r] .. csr_ptr[r+1]), the top bit marking a J2 bond
   const long long *csr_ptr;
