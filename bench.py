@@ -8,7 +8,9 @@ Default workload: the L = 26 XXZ chain (J2 = 0, Delta = 1, W = 4, seed 5;
 block size 64.  A full solve there needs about 2e5 Chebyshev steps per
 Lanczos block and hours of filtering, so one bench step is a fixed segment of
 that solve: one ``polfed_solve`` with the filter order fixed at K (default
-64) and two Lanczos blocks -- every stage of the path (bounds Lanczos, start
+256; the real order is ~1e3 times larger, so the stages outside the filter
+weigh more here than in a solve) and two Lanczos blocks -- every stage of
+the path (bounds Lanczos, start
 block, the Chebyshev filter, Lan1, full reorthogonalisation, CholeskyQR2, the
 T_m eigensolve, Rayleigh-Ritz, selection, residuals) at the full 10,400,600
 rows, in FP64; its status is NOT_CONVERGED by construction.  The metric is H.V
@@ -204,7 +206,7 @@ def main():
     ap.add_argument("--workload", default="c5",
                     choices=["c1", "c2", "c3_fp32", "c3_fp64", "c4", "c5", "c5_fp32",
                              "j1j2_L20_nev100", "j1j2_L22_nev100", "j1j2_L22_nev200"])
-    ap.add_argument("--K", type=int, default=64, help="fixed filter order of a c5 step")
+    ap.add_argument("--K", type=int, default=256, help="fixed filter order of a c5 step")
     ap.add_argument("--blocks", type=int, default=2, help="Lanczos blocks of a c5 step")
     ap.add_argument("--shape", default="",
                     help="step shape threads,lpl,wg_per_cu,lds_tables,early_loads,rank_incremental,"
