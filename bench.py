@@ -23,7 +23,9 @@ oracle's throughput on the host cores.
 
 Other workloads (``--workload c1 | c2 | c3_fp32 | c3_fp64 | c4`` and the
 paper's J1-J2 timing points ``j1j2_L20_nev100 | j1j2_L22_nev100 |
-j1j2_L22_nev200``) time complete solves (time to N_ev).
+j1j2_L22_nev200``) time complete solves (time to N_ev); for them ``--dos
+kpm`` takes the filter order from the kernel-polynomial density of states
+and ``--target`` moves the target off the middle of the spectrum.
 """
 
 import argparse
@@ -212,6 +214,11 @@ def main():
                     help="step shape threads,lpl,wg_per_cu,lds_tables,early_loads,rank_incremental,"
                          "xcd_slices (else the profiled one, else the built-in default / tuned)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dos", choices=["gauss", "kpm"], default="gauss",
+                    help="density of states of the order rule (complete-solve workloads)")
+    ap.add_argument("--target", type=float, default=None,
+                    help="rescaled target energy in (0, 1) of the complete-solve workloads "
+                         "(default: the workload's, 0.5)")
     ap.add_argument("--no-fp32", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -269,7 +276,8 @@ def main():
                                precision=prec, target_kind=0, target=wl.eps_target)
     else:
         opts = pf.default_opts(block_size=wl.block, K=wl.K, precision=prec, target_kind=0,
-                               target=wl.eps_target)
+                               target=args.target if args.target is not None else wl.eps_target,
+                               dos=pf.DOS_KPM if args.dos == "kpm" else pf.DOS_GAUSS)
 
     def step():
         if len(models) == 1:
@@ -338,6 +346,8 @@ def main():
                    "lanczos_blocks": last["m"] if len(models) == 1 else
                    [min(i["m"] for i in infos), max(i["m"] for i in infos)],
                    "precision": "fp64" if prec == 0 else "fp32", "autotune_s": tune_s,
+                   "dos": args.dos if not big else "gauss",
+                   "target_eps": opts.target,
                    "filter_form": form_times, "step_shape": shape},
         "statuses": sorted(set(int(x) for x in statuses)),
         "solve": {k: last[k] for k in ("t_bounds", "t_filter", "t_orth", "t_eig", "t_rr",

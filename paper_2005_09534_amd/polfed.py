@@ -30,6 +30,9 @@ class Model(ctypes.Structure):
                 ("h", P_double)]
 
 
+DOS_GAUSS, DOS_KPM = 0, 1
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("target_kind", c_int), ("target", c_double), ("block_size", c_int),
                 ("K", c_ll), ("p", c_double), ("precision", c_int),
