@@ -176,6 +176,7 @@ void dos_moments(polfed_ctx *ctx, const Chain &c, double a, double b, int nmom, 
   std::vector<double> h(ndots);
   PF_HIP(hipMemcpyAsync(h.data(), dots, sizeof(double) * ndots, hipMemcpyDeviceToHost, st));
   PF_HIP(hipStreamSynchronize(st));
+  ctx->buf("dos_t").release();  // 3 n S values: not kept for the solve that follows
   // sums over the chunks, in chunk order
   std::vector<double> d0(m + 1, 0.0), d1(m + 1, 0.0);
   for (int ch = 0; ch < nchunk; ++ch)

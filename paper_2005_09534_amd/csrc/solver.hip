@@ -1859,6 +1859,7 @@ static int solve_batch_impl(polfed_ctx *ctx, int R, const polfed_model *models,
       t_rfilt += tc - tb;
       t_fin += now_s() - tc;
     }
+    ctx->buf("ref_cheb").release();  // up to 4 GiB of refinement recurrence buffers
     if (std::getenv("POLFED_VERBOSE"))
       fprintf(stderr, "[polfed] batch finalize: Rayleigh-Ritz %.2f s, refinement prepare %.2f s, "
                       "filters %.2f s, orthonormalisation and Rayleigh-Ritz %.2f s\n",
