@@ -99,9 +99,18 @@ typedef struct {
                              DOS is not Gaussian at the target            */
   int dos_moments;        /* KPM moments M; 0 -> 256                       */
   int dos_vectors;        /* KPM random vectors; 0 -> 4                    */
+  int damping;            /* POLFED_DAMP_NONE (default: the paper's raw
+                             delta expansion of eq. (polyTransf)) or
+                             POLFED_DAMP_JACKSON: c_n g_n with the Jackson
+                             factors of the K+1 coefficients, which removes
+                             the side lobes and widens the main lobe about
+                             twofold; the order rule then counts states in
+                             the damped filter's lobe (polfed_filter_coeffs,
+                             polfed_filter_order_damped)                  */
 } polfed_opts;
 
 enum polfed_dos { POLFED_DOS_GAUSS = 0, POLFED_DOS_KPM = 1 };
+enum polfed_damping { POLFED_DAMP_NONE = 0, POLFED_DAMP_JACKSON = 1 };
 
 /* Per-solve record (all times in seconds, wall clock on the host). */
 typedef struct {
@@ -166,6 +175,24 @@ int polfed_filter_order(const polfed_model *model, double E0w, double E1w,
                         double sigma_tilde, int nwin, double p,
                         long long *K, double *rho);
 
+/* Filter coefficients with optional damping: c[n] = c_n of
+ * polfed_cheb_coeffs times g_n, where for damping = POLFED_DAMP_JACKSON
+ * g_n = [(M-n+1) cos(pi n/(M+1)) + sin(pi n/(M+1)) cot(pi/(M+1))]/(M+1),
+ * M = K+1 (Jackson's kernel; Weisse et al., Rev. Mod. Phys. 78, 275), and
+ * g_n = 1 for POLFED_DAMP_NONE; *D = sum_n c[n] T_n(sigma_tilde), so that
+ * P(sigma_tilde) = 1.  c: host array of K+1.  The damped P is non-negative
+ * on [-1, 1]. */
+int polfed_filter_coeffs(double sigma_tilde, long long K, int damping, double *c, double *D);
+/* polfed_filter_order and polfed_window_order for a damped filter: the
+ * main lobe {P_K >= p} is that of the damped P (in closed form: with x =
+ * cos theta, sigma_tilde = cos alpha, P(x) = [F(theta-alpha) +
+ * F(theta+alpha)]/[F(0) + F(2 alpha)], F(u) = (E(u+beta) + E(u-beta))^2,
+ * E(u) = sin(M u/2)/sin(u/2), beta = pi/(M+1)); *K the order and *nwin_out
+ * the window after the cap max_order (<= 0: no cap). */
+int polfed_filter_order_damped(const polfed_model *model, double E0w, double E1w,
+                               double sigma_tilde, int nwin, double p, int damping,
+                               long long max_order, int *nwin_out, long long *K);
+
 /* The order cap of the FP32 filter (polfed_opts.max_order): the smallest
  * window count *nwin_out >= nwin whose order from polfed_filter_order is at
  * most max_order, and that order *K (max_order <= 0: no cap, the window
@@ -187,11 +214,12 @@ int polfed_kpm_count(const double *mu, int nmom, long long N, double x_lo, doubl
                      double *count);
 /* The order rule of polfed_filter_order with the KPM count in place of the
  * Gaussian: *K = max{K : count(main lobe {P_K >= p} around sigma_tilde) >=
- * nwin}; with max_order > 0 and that K above it, the smallest window
- * *nwin_out >= nwin whose order is at most max_order, as in
+ * nwin}, the lobe that of the filter with the given damping
+ * (POLFED_DAMP_*); with max_order > 0 and that K above it, the smallest
+ * window *nwin_out >= nwin whose order is at most max_order, as in
  * polfed_window_order (else *nwin_out = nwin). */
 int polfed_kpm_order(const double *mu, int nmom, long long N, double sigma_tilde, int nwin,
-                     double p, long long max_order, int *nwin_out, long long *K);
+                     double p, int damping, long long max_order, int *nwin_out, long long *K);
 
 /* ---- stage calls (device pointers, async on the context stream) -------- */
 
@@ -342,6 +370,10 @@ int polfed_set_graphs(polfed_ctx *ctx, int on);
 #define POLFED_FORM_CLENSHAW 0
 #define POLFED_FORM_FORWARD 1
 int polfed_set_filter_form(polfed_ctx *ctx, int form);
+/* Damping of the filter coefficients in polfed_apply_filter
+ * (POLFED_DAMP_NONE, the default, or POLFED_DAMP_JACKSON; polfed_solve takes
+ * it from its options). */
+int polfed_set_filter_damping(polfed_ctx *ctx, int damping);
 /* Filter counters accumulated by the context since the last reset (or the
  * start of the last polfed_solve): kernel time of the Chebyshev steps by HIP
  * events on the context's stream (seconds), step launches, and algorithmic

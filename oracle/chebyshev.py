@@ -23,8 +23,16 @@ Gamma).  Readings (the paper is terse here):
 * K = max{K : n_P(K) >= N_ev}; found by doubling then bisection on K; lobe
   edges by bisection in theta (x = cos theta).
 
+Optional damped variant (not in the paper, whose expansion is undamped):
+c_n times the Jackson factors g_n of the K+1 coefficients (``kpm.jackson``),
+D again sum_n c_n T_n(sigma); the lobe edges and the order rule are those of
+the damped P, evaluated here by its definition sum.
+
 Parity pins: the Dirichlet-kernel closed form of P, D at sigma = 0,
-P(H~)v = P(lambda~)v on eigenvectors, the asymptotic K formula.
+P(H~)v = P(lambda~)v on eigenvectors, the asymptotic K formula; for the
+damped P: non-negative everywhere, equal to pi sqrt(1 - x^2) times the
+KPM density of a single level at sigma (up to D), and its lobe half-width
+tending to 1.8265 pi/(K+2).
 """
 
 from math import erf, sqrt, pi
@@ -40,17 +48,28 @@ def cheb_coeffs(sigma, K):
     return c
 
 
-def norm_D(sigma, K):
-    """D = sum_n c_n T_n(sigma), so that P(sigma) = 1."""
+def filter_coeffs(sigma, K, damping=0):
+    """c_n of eq. (polyTransf), times the Jackson factors g_n of the K+1
+    coefficients when damping = 1 (the optional damped variant; the paper's
+    filter is undamped)."""
     c = cheb_coeffs(sigma, K)
+    if damping:
+        from . import kpm
+        c = c * kpm.jackson(K + 1)
+    return c
+
+
+def norm_D(sigma, K, damping=0):
+    """D = sum_n c_n T_n(sigma), so that P(sigma) = 1."""
+    c = filter_coeffs(sigma, K, damping)
     n = np.arange(K + 1, dtype=np.float64)
     return float(np.sum(c * np.cos(n * np.arccos(sigma))))
 
 
-def P_of_x(x, sigma, K):
+def P_of_x(x, sigma, K, damping=0):
     """P^K_sigma(x) by its definition: (1/D) sum c_n cos(n arccos x)."""
-    c = cheb_coeffs(sigma, K)
-    D = norm_D(sigma, K)
+    c = filter_coeffs(sigma, K, damping)
+    D = norm_D(sigma, K, damping)
     x = np.atleast_1d(np.asarray(x, dtype=np.float64))
     n = np.arange(K + 1, dtype=np.float64)
     th = np.arccos(np.clip(x, -1.0, 1.0))
@@ -64,12 +83,12 @@ def rescale_coeffs(E0, E1):
     return a, b
 
 
-def filter_block(H, X, E0, E1, sigma, K):
+def filter_block(H, X, E0, E1, sigma, K, damping=0):
     """Y = P^K_sigma(H~) X by the forward recurrence, FP64.
     H: scipy sparse (n x n) FP64; X: (n x s)."""
     a, b = rescale_coeffs(E0, E1)
-    c = cheb_coeffs(sigma, K)
-    D = norm_D(sigma, K)
+    c = filter_coeffs(sigma, K, damping)
+    D = norm_D(sigma, K, damping)
 
     def Ht(V):
         return a * (H @ V) + b * V
@@ -116,14 +135,16 @@ def _P_theta(theta, sigma, K, c, D):
     return float(np.dot(np.cos(n * theta), c) / D)
 
 
-def lobe_edges(sigma, K, p, iters=200):
+def lobe_edges(sigma, K, p, iters=200, damping=0):
     """Edges (x_lo, x_hi) of the main lobe {P_K >= p} around sigma, by
-    bisection in theta on [alpha, alpha + 2 pi/(2K+1)] (right) and
-    [alpha - 2 pi/(2K+1), alpha] (left), clipped to [0, pi]."""
-    c = cheb_coeffs(sigma, K)
-    D = norm_D(sigma, K)
+    bisection in theta on [alpha, alpha + w] (right) and [alpha - w, alpha]
+    (left), clipped to [0, pi]; w = 2 pi/(2K+1), the first zero of the
+    undamped kernel, or 6 pi/(K+2) for the damped filter (its kernel's first
+    zero is near 3 pi/(K+2) and its side lobes are far below p)."""
+    c = filter_coeffs(sigma, K, damping)
+    D = norm_D(sigma, K, damping)
     alpha = float(np.arccos(sigma))
-    w = 2.0 * pi / (2 * K + 1)
+    w = 6.0 * pi / (K + 2) if damping else 2.0 * pi / (2 * K + 1)
 
     def edge(t_in, t_out):
         # P(t_in) >= p; find crossing towards t_out
@@ -144,17 +165,17 @@ def lobe_edges(sigma, K, p, iters=200):
     return float(np.cos(th_r)), float(np.cos(th_l))
 
 
-def n_P(K, sigma, p, N, Ebar, Gamma, E0, E1):
+def n_P(K, sigma, p, N, Ebar, Gamma, E0, E1, damping=0):
     """Estimated number of eigenvalues of P^K(H~) that are >= p."""
-    x_lo, x_hi = lobe_edges(sigma, K, p)
+    x_lo, x_hi = lobe_edges(sigma, K, p, damping=damping)
     Elo = 0.5 * (x_lo * (E1 - E0) + (E1 + E0))
     Ehi = 0.5 * (x_hi * (E1 - E0) + (E1 + E0))
     return n_states_between(N, Ebar, Gamma, Elo, Ehi)
 
 
-def choose_K(nev, sigma, p, N, Ebar, Gamma, E0, E1, K_max=1 << 26):
+def choose_K(nev, sigma, p, N, Ebar, Gamma, E0, E1, K_max=1 << 26, damping=0):
     """K = max{K >= 1 : n_P(K) >= nev}.  Doubling from K=1, then bisection."""
-    f = lambda K: n_P(K, sigma, p, N, Ebar, Gamma, E0, E1)
+    f = lambda K: n_P(K, sigma, p, N, Ebar, Gamma, E0, E1, damping)
     if f(1) < nev:
         return 1
     lo = 1
@@ -174,7 +195,7 @@ def choose_K(nev, sigma, p, N, Ebar, Gamma, E0, E1, K_max=1 << 26):
     return lo
 
 
-def capped_window(nwin, sigma, p, N, Ebar, Gamma, E0, E1, K_cap):
+def capped_window(nwin, sigma, p, N, Ebar, Gamma, E0, E1, K_cap, damping=0):
     """Window count under a cap on the order (the FP32 filter's rounding
     error grows like sqrt(K)): the smallest N_win >= nwin whose order
     choose_K(N_win) is at most K_cap, found by scanning upward.  A wider
@@ -184,7 +205,7 @@ def capped_window(nwin, sigma, p, N, Ebar, Gamma, E0, E1, K_cap):
     one fewer does not) and by the paper's K ~ 1/N_win law."""
     w = int(nwin)
     while True:
-        K = choose_K(w, sigma, p, N, Ebar, Gamma, E0, E1)
+        K = choose_K(w, sigma, p, N, Ebar, Gamma, E0, E1, damping=damping)
         if K <= K_cap or w >= N:
             return w, K
         w += 1

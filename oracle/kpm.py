@@ -119,16 +119,16 @@ def count(mu, N, x_lo, x_hi):
     return N * total / pi
 
 
-def n_P(K, sigma, p, mu, N):
+def n_P(K, sigma, p, mu, N, damping=0):
     """States of the KPM density inside the main lobe {P_K >= p}."""
-    x_lo, x_hi = chebyshev.lobe_edges(sigma, K, p)
+    x_lo, x_hi = chebyshev.lobe_edges(sigma, K, p, damping=damping)
     return count(mu, N, x_lo, x_hi)
 
 
-def choose_K(nev, sigma, p, mu, N, K_max=1 << 26):
+def choose_K(nev, sigma, p, mu, N, K_max=1 << 26, damping=0):
     """K = max{K >= 1 : n_P(K) >= nev} with the KPM count.  Doubling from
     K = 1, then bisection (n_P falls with K)."""
-    f = lambda K: n_P(K, sigma, p, mu, N)
+    f = lambda K: n_P(K, sigma, p, mu, N, damping)
     if f(1) < nev:
         return 1
     lo, hi = 1, 2

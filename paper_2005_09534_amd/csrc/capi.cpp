@@ -130,6 +130,7 @@ void polfed_default_opts(polfed_opts *o) {
   o->dos = POLFED_DOS_GAUSS;
   o->dos_moments = 256;
   o->dos_vectors = 4;
+  o->damping = POLFED_DAMP_NONE;
 }
 
 // Message of the last failed polfed_create on this host thread (there is no
@@ -215,6 +216,36 @@ int polfed_cheb_coeffs(double sigma, long long K, double *c, double *D) {
   return POLFED_OK;
 }
 
+int polfed_filter_coeffs(double sigma, long long K, int damping, double *c, double *D) {
+  if (!c || !D || K < 0 || !(std::fabs(sigma) < 1.0) ||
+      (damping != POLFED_DAMP_NONE && damping != POLFED_DAMP_JACKSON))
+    return POLFED_EINVAL;
+  std::vector<double> v;
+  double d;
+  cheb_coeffs(sigma, K, v, d, damping);
+  std::memcpy(c, v.data(), sizeof(double) * (size_t)(K + 1));
+  *D = d;
+  return POLFED_OK;
+}
+
+int polfed_filter_order_damped(const polfed_model *m, double E0w, double E1w, double sigma,
+                               int nwin, double p, int damping, long long max_order,
+                               int *nwin_out, long long *K) {
+  if (!m || !m->h || !K || !nwin_out || nwin < 1 || !(E1w > E0w) || !(std::fabs(sigma) < 1.0) ||
+      !(p > 0.0) || (damping != POLFED_DAMP_NONE && damping != POLFED_DAMP_JACKSON))
+    return POLFED_EINVAL;
+  long long n = polfed_dim(m->L);
+  if (n < 0) return POLFED_EINVAL;
+  const double Gamma = dos_gamma(m->L, m->J1, m->J2, m->Delta, m->h);
+  const double Ebar = trace_mean(m->L, m->J1, m->J2, m->Delta);
+  const int nw = (int)std::min<long long>(nwin, n);
+  *K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nw, p, nullptr, damping);
+  *nwin_out = nw;
+  if (max_order > 0 && *K > max_order)
+    *nwin_out = capped_window(n, Ebar, Gamma, E0w, E1w, sigma, nw, p, max_order, K, damping);
+  return POLFED_OK;
+}
+
 int polfed_filter_order(const polfed_model *m, double E0w, double E1w, double sigma, int nwin,
                         double p, long long *K, double *rho) {
   if (!m || !m->h || !K || nwin < 1 || !(E1w > E0w) || !(std::fabs(sigma) < 1.0) || !(p > 0.0))
@@ -251,15 +282,16 @@ int polfed_kpm_count(const double *mu, int nmom, long long N, double x_lo, doubl
 }
 
 int polfed_kpm_order(const double *mu, int nmom, long long N, double sigma, int nwin, double p,
-                     long long max_order, int *nwin_out, long long *K) {
+                     int damping, long long max_order, int *nwin_out, long long *K) {
   if (!mu || !K || !nwin_out || nmom < 1 || N < 1 || nwin < 1 || !(std::fabs(sigma) < 1.0) ||
-      !(p > 0.0))
+      !(p > 0.0) || (damping != POLFED_DAMP_NONE && damping != POLFED_DAMP_JACKSON))
     return POLFED_EINVAL;
   const std::vector<double> m(mu, mu + nmom);
   const int nw = (int)std::min<long long>(nwin, N);
-  *K = choose_order_kpm(m, N, sigma, nw, p);
+  *K = choose_order_kpm(m, N, sigma, nw, p, damping);
   *nwin_out = nw;
-  if (max_order > 0 && *K > max_order) *nwin_out = capped_window_kpm(m, N, sigma, nw, p, max_order, K);
+  if (max_order > 0 && *K > max_order)
+    *nwin_out = capped_window_kpm(m, N, sigma, nw, p, max_order, K, damping);
   return POLFED_OK;
 }
 
@@ -543,6 +575,15 @@ int polfed_set_filter_form(polfed_ctx *ctx, int form) {
     PF_REQUIRE(form == POLFED_FORM_CLENSHAW || form == POLFED_FORM_FORWARD,
                "form must be POLFED_FORM_CLENSHAW or POLFED_FORM_FORWARD");
     ctx->filter_form = form;
+    return POLFED_OK;
+  });
+}
+
+int polfed_set_filter_damping(polfed_ctx *ctx, int damping) {
+  return guarded(ctx, [&] {
+    PF_REQUIRE(damping == POLFED_DAMP_NONE || damping == POLFED_DAMP_JACKSON,
+               "damping must be POLFED_DAMP_NONE or POLFED_DAMP_JACKSON");
+    ctx->filter_damping = damping;
     return POLFED_OK;
   });
 }

@@ -342,13 +342,15 @@ double stream_copy_gbs(hipStream_t st, const void *src, void *dst, long long byt
 // ------------------------------------------------------------ host math --
 
 // plan.cpp
-void cheb_coeffs(double sigma, long long K, std::vector<double> &c, double &D);
+// (damping: POLFED_DAMP_NONE, the paper's raw delta expansion, or
+// POLFED_DAMP_JACKSON; the order rules then use the damped filter's lobe)
+void cheb_coeffs(double sigma, long long K, std::vector<double> &c, double &D, int damping = 0);
 double dos_gamma(int L, double J1, double J2, double Delta, const double *h);
 double trace_mean(int L, double J1, double J2, double Delta);
 long long choose_order(long long N, double Ebar, double Gamma, double E0w, double E1w,
-                       double sigma, int nwin, double p, double *rho);
+                       double sigma, int nwin, double p, double *rho, int damping = 0);
 int capped_window(long long N, double Ebar, double Gamma, double E0w, double E1w, double sigma,
-                  int nwin, double p, long long K_cap, long long *K);
+                  int nwin, double p, long long K_cap, long long *K, int damping = 0);
 // Kernel polynomial method (density of states from Chebyshev moments mu of
 // H~, Jackson damping): the number of states in [x_lo, x_hi], the density at
 // x, and the order rule and FP32 cap with that density in place of the
@@ -357,9 +359,9 @@ void jackson(int M, std::vector<double> &g);
 double kpm_count(const std::vector<double> &mu, long long N, double x_lo, double x_hi);
 double kpm_density(const std::vector<double> &mu, double x);
 long long choose_order_kpm(const std::vector<double> &mu, long long N, double sigma, int nwin,
-                           double p);
+                           double p, int damping = 0);
 int capped_window_kpm(const std::vector<double> &mu, long long N, double sigma, int nwin,
-                      double p, long long K_cap, long long *K);
+                      double p, long long K_cap, long long *K, int damping = 0);
 // dos.hip: Chebyshev moments mu_0 .. mu_{nmom-1} of H~ = aH + b from the nvec
 // columns of R (device, n x nvec row-major; NULL: +-1 entries from Philox
 // keyed by seed), mu_n = sum_r <r|T_n|r> / sum_r <r|r>, into mu (host).
@@ -405,6 +407,7 @@ struct polfed_ctx {
   std::vector<unsigned long long> filter_graph_key;
   int use_graphs = 1;
   int filter_form = 0;  // POLFED_FORM_CLENSHAW or POLFED_FORM_FORWARD
+  int filter_damping = 0;  // POLFED_DAMP_* of polfed_apply_filter
   polfed::DevBuf &buf(const std::string &name) {
     auto &p = bufs[name];
     if (!p) p.reset(new polfed::DevBuf());

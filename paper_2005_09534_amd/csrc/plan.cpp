@@ -20,7 +20,7 @@
 
 namespace polfed {
 
-void cheb_coeffs(double sigma, long long K, std::vector<double> &c, double &D) {
+void cheb_coeffs(double sigma, long long K, std::vector<double> &c, double &D, int damping) {
   c.assign((size_t)K + 1, 0.0);
   if (sigma == 0.0) {
     // cos(n pi/2) exactly: 1, 0, -1, 0, ...
@@ -32,6 +32,20 @@ void cheb_coeffs(double sigma, long long K, std::vector<double> &c, double &D) {
   } else {
     const double a = std::acos(sigma);
     for (long long n = 0; n <= K; ++n) c[n] = (n == 0 ? 1.0 : 2.0) * std::cos((double)n * a);
+  }
+  if (damping == POLFED_DAMP_JACKSON) {
+    // Jackson damping of the delta expansion: c_n g_n, g_n the Jackson
+    // factors for the K + 1 coefficients, D again sum_n c_n T_n(sigma)
+    std::vector<double> g;
+    jackson((int)(K + 1), g);
+    const double a = std::acos(sigma);
+    double s = 0.0;
+    for (long long n = 0; n <= K; ++n) {
+      c[n] *= g[n];
+      s += c[n] * std::cos((double)n * a);
+    }
+    D = s;
+    return;
   }
   // D = sum_n c_n T_n(sigma) = 1 + 2 sum_{n>=1} cos^2(n alpha)
   if (sigma == 0.0) {
@@ -68,14 +82,45 @@ static double P_theta(double theta, double alpha, long long K) {
   return num / den;
 }
 
+// The Jackson-damped filter in closed form.  The Jackson factors of M
+// coefficients are the autocorrelation of a_v = sin(beta (v+1)), beta =
+// pi/(M+1), so 1 + 2 sum_{n>=1} g_n cos(n phi) = |A(phi)|^2 / sum a_v^2 with
+// A(phi) = sum_v a_v e^{i v phi}; summing the two geometric series,
+// |A(phi)| = |E_M(phi + beta) + E_M(phi - beta)| / 2 with E_M(u) =
+// sin(M u/2)/sin(u/2).  As for the undamped filter,
+//     P^J_K(cos theta) = [F(theta-alpha) + F(theta+alpha)] / [F(0) + F(2 alpha)],
+// F(phi) = (E_M(phi+beta) + E_M(phi-beta))^2, M = K + 1.
+static double dirichlet_m(double u, long long M) {
+  const double sh = std::sin(0.5 * u);
+  if (std::fabs(sh) < 1e-12) return (double)M * std::cos(0.5 * (double)M * u) / std::cos(0.5 * u);
+  return std::sin(0.5 * (double)M * u) / sh;
+}
+
+static double jackson_F(double phi, long long M) {
+  const double beta = M_PI / ((double)M + 1.0);
+  const double v = dirichlet_m(phi + beta, M) + dirichlet_m(phi - beta, M);
+  return v * v;
+}
+
+static double P_theta_jackson(double theta, double alpha, long long K) {
+  const long long M = K + 1;
+  return (jackson_F(theta - alpha, M) + jackson_F(theta + alpha, M)) /
+         (jackson_F(0.0, M) + jackson_F(2.0 * alpha, M));
+}
+
+static double P_theta_of(int damping, double theta, double alpha, long long K) {
+  return damping == POLFED_DAMP_JACKSON ? P_theta_jackson(theta, alpha, K)
+                                        : P_theta(theta, alpha, K);
+}
+
 // Bisection on [alpha, t_out] for the crossing P = p; P(alpha) = 1 >= p.
-static double lobe_edge(double alpha, double t_out, long long K, double p) {
+static double lobe_edge(double alpha, double t_out, long long K, double p, int damping) {
   double t_in = alpha;
-  if (P_theta(t_out, alpha, K) >= p) return t_out;
+  if (P_theta_of(damping, t_out, alpha, K) >= p) return t_out;
   for (int it = 0; it < 200; ++it) {
     const double mid = 0.5 * (t_in + t_out);
     if (mid == t_in || mid == t_out) break;
-    if (P_theta(mid, alpha, K) >= p)
+    if (P_theta_of(damping, mid, alpha, K) >= p)
       t_in = mid;
     else
       t_out = mid;
@@ -83,20 +128,24 @@ static double lobe_edge(double alpha, double t_out, long long K, double p) {
   return t_in;
 }
 
-// Edges (x_lo, x_hi) of the main lobe {P_K >= p} around sigma.
-static void lobe(long long K, double sigma, double p, double &x_lo, double &x_hi) {
+// Edges (x_lo, x_hi) of the main lobe {P_K >= p} around sigma: searched
+// within the first zero of the undamped kernel (2 pi/(2K+1) from alpha) or,
+// damped, within twice the damped kernel's first zero (3 pi/(K+2)); beyond
+// those the side lobes stay below p.
+static void lobe(long long K, double sigma, double p, double &x_lo, double &x_hi, int damping) {
   const double alpha = std::acos(sigma);
-  const double w = 2.0 * M_PI / (2.0 * (double)K + 1.0);
-  const double th_r = lobe_edge(alpha, std::min(alpha + w, M_PI), K, p);
-  const double th_l = lobe_edge(alpha, std::max(alpha - w, 0.0), K, p);
+  const double w = damping == POLFED_DAMP_JACKSON ? 6.0 * M_PI / ((double)K + 2.0)
+                                                  : 2.0 * M_PI / (2.0 * (double)K + 1.0);
+  const double th_r = lobe_edge(alpha, std::min(alpha + w, M_PI), K, p, damping);
+  const double th_l = lobe_edge(alpha, std::max(alpha - w, 0.0), K, p, damping);
   x_lo = std::cos(th_r);
   x_hi = std::cos(th_l);
 }
 
 static double n_in_window(long long K, double sigma, double p, long long N, double Ebar,
-                          double Gamma, double E0w, double E1w) {
+                          double Gamma, double E0w, double E1w, int damping) {
   double x_lo, x_hi;
-  lobe(K, sigma, p, x_lo, x_hi);
+  lobe(K, sigma, p, x_lo, x_hi, damping);
   const double Elo = 0.5 * (x_lo * (E1w - E0w) + (E1w + E0w));
   const double Ehi = 0.5 * (x_hi * (E1w - E0w) + (E1w + E0w));
   const double s = std::sqrt(2.0) * Gamma;
@@ -125,14 +174,15 @@ static long long order_rule(F &&f, int nwin) {
 }
 
 long long choose_order(long long N, double Ebar, double Gamma, double E0w, double E1w,
-                       double sigma, int nwin, double p, double *rho) {
+                       double sigma, int nwin, double p, double *rho, int damping) {
   if (rho) {
     const double E = 0.5 * (sigma * (E1w - E0w) + (E1w + E0w));
     *rho = (double)N * (E1w - E0w) / (2.0 * std::sqrt(2.0 * M_PI) * Gamma) *
            std::exp(-(E - Ebar) * (E - Ebar) / (2.0 * Gamma * Gamma));
   }
   return order_rule(
-      [&](long long K) { return n_in_window(K, sigma, p, N, Ebar, Gamma, E0w, E1w); }, nwin);
+      [&](long long K) { return n_in_window(K, sigma, p, N, Ebar, Gamma, E0w, E1w, damping); },
+      nwin);
 }
 
 // ---- density of states by the kernel polynomial method --------------------
@@ -174,11 +224,11 @@ double kpm_density(const std::vector<double> &mu, double x) {
 }
 
 long long choose_order_kpm(const std::vector<double> &mu, long long N, double sigma, int nwin,
-                           double p) {
+                           double p, int damping) {
   return order_rule(
       [&](long long K) {
         double x_lo, x_hi;
-        lobe(K, sigma, p, x_lo, x_hi);
+        lobe(K, sigma, p, x_lo, x_hi, damping);
         return kpm_count(mu, N, x_lo, x_hi);
       },
       nwin);
@@ -215,16 +265,19 @@ static int capped_window_by(O &&order, long long N, int nwin, long long K_cap, l
 }
 
 int capped_window(long long N, double Ebar, double Gamma, double E0w, double E1w, double sigma,
-                  int nwin, double p, long long K_cap, long long *K) {
+                  int nwin, double p, long long K_cap, long long *K, int damping) {
   return capped_window_by(
-      [&](long long w) { return choose_order(N, Ebar, Gamma, E0w, E1w, sigma, (int)w, p, nullptr); },
+      [&](long long w) {
+        return choose_order(N, Ebar, Gamma, E0w, E1w, sigma, (int)w, p, nullptr, damping);
+      },
       N, nwin, K_cap, K);
 }
 
 int capped_window_kpm(const std::vector<double> &mu, long long N, double sigma, int nwin,
-                      double p, long long K_cap, long long *K) {
+                      double p, long long K_cap, long long *K, int damping) {
   return capped_window_by(
-      [&](long long w) { return choose_order_kpm(mu, N, sigma, (int)w, p); }, N, nwin, K_cap, K);
+      [&](long long w) { return choose_order_kpm(mu, N, sigma, (int)w, p, damping); }, N, nwin,
+      K_cap, K);
 }
 
 // ---- tridiagonal extremes (bounds Lanczos) --------------------------------

@@ -517,6 +517,8 @@ static polfed_opts resolve_opts(const polfed_opts *in) {
   if (o.dos_moments <= 0) o.dos_moments = 256;
   if (o.dos_vectors <= 0) o.dos_vectors = 4;
   PF_REQUIRE(o.dos == POLFED_DOS_GAUSS || o.dos == POLFED_DOS_KPM, "dos must be 0 or 1");
+  PF_REQUIRE(o.damping == POLFED_DAMP_NONE || o.damping == POLFED_DAMP_JACKSON,
+             "damping must be 0 or 1");
   PF_REQUIRE(o.dos_moments <= (1 << 20), "dos_moments must be at most 2^20");
   PF_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
   PF_REQUIRE(o.target_kind == 0 || o.target_kind == 1, "target_kind must be 0 or 1");
@@ -674,18 +676,20 @@ void Realization<T>::setup(polfed_ctx *ctx_, const polfed_model *model, const po
       // kernel polynomial DOS from Chebyshev moments of this H~
       std::vector<double> mu;
       dos_moments(ctx, c, a, b, o.dos_moments, o.dos_vectors, nullptr, o.seed ^ 0xd05d05ull, mu);
-      K = choose_order_kpm(mu, n, sigma, nwin, o.p);
-      if (fp32 && K > cap) nwin = capped_window_kpm(mu, n, sigma, nwin, o.p, cap, &K);
+      K = choose_order_kpm(mu, n, sigma, nwin, o.p, o.damping);
+      if (fp32 && K > cap)
+        nwin = capped_window_kpm(mu, n, sigma, nwin, o.p, cap, &K, o.damping);
     } else {
       double rho = 0.0;
       const double Gamma = dos_gamma(c.L, c.J1, c.J2, c.Delta, c.h);
       const double Ebar = trace_mean(c.L, c.J1, c.J2, c.Delta);
-      K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, &rho);
-      if (fp32 && K > cap) nwin = capped_window(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, cap, &K);
+      K = choose_order(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, &rho, o.damping);
+      if (fp32 && K > cap)
+        nwin = capped_window(n, Ebar, Gamma, E0w, E1w, sigma, nwin, o.p, cap, &K, o.damping);
     }
     if (nwin != nwin0) o.window_factor = std::max(o.window_factor, (double)nwin / nev);
   }
-  cheb_coeffs(sigma, K, coef, D);
+  cheb_coeffs(sigma, K, coef, D, o.damping);
   // column cap: 8 N_win + 8 s in whole blocks, at most n, and the Lanczos
   // basis within half of the device memory free now (the Rayleigh-Ritz
   // step needs room for three more blocks of the candidates' width)
@@ -1167,7 +1171,7 @@ void Realization<T>::refine_prepare() {
   const std::vector<int> near = nearest(Efin, std::vector<char>(Efin.size(), 1), q);
   PF_HIP(hipMemcpyAsync(didx, near.data(), sizeof(int) * q, hipMemcpyHostToDevice, st));
   launch_gather_cols(st, n, q, WRb.as<double>(), ldr, didx, Vnb.as<double>(), ldr);
-  cheb_coeffs(sigma, K_r, coef_r, D_r);
+  cheb_coeffs(sigma, K_r, coef_r, D_r, o.damping);
 }
 
 // UR <- P^{K_r}(H~) Vn with the single-chain FP64 filter, in whole
@@ -2045,7 +2049,7 @@ void stage_apply_filter(polfed_ctx *ctx, const Chain &c, double E0, double E1, d
   T *bufs = static_cast<T *>(ctx->buf("stage_cheb").ensure(sizeof(T) * 3 * (size_t)n * nvec));
   std::vector<double> coef;
   double D;
-  cheb_coeffs(sigma, K, coef, D);
+  cheb_coeffs(sigma, K, coef, D, ctx->filter_damping);
   run_filter<T>(ctx, c, dt, a, nvec, X, nvec, Y, nvec, K, coef, D, bufs, sizeof(T) == 4, nullptr);
 }
 

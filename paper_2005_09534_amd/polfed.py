@@ -31,6 +31,7 @@ class Model(ctypes.Structure):
 
 
 DOS_GAUSS, DOS_KPM = 0, 1
+DAMP_NONE, DAMP_JACKSON = 0, 1
 
 
 class Opts(ctypes.Structure):
@@ -39,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("window_factor", c_double), ("max_cols", c_int), ("tol", c_double),
                 ("eta", c_double), ("bounds_steps", c_int), ("seed", c_ull),
                 ("max_order", c_ll), ("dos", c_int), ("dos_moments", c_int),
-                ("dos_vectors", c_int)]
+                ("dos_vectors", c_int), ("damping", c_int)]
 
 
 class Info(ctypes.Structure):
@@ -118,8 +119,13 @@ def _load():
                                         ctypes.POINTER(c_int), P_double]),
         "polfed_gap_ratio": (c_int, [P_double, c_int, P_double]),
         "polfed_kpm_count": (c_int, [P_double, c_int, c_ll, c_double, c_double, P_double]),
-        "polfed_kpm_order": (c_int, [P_double, c_int, c_ll, c_double, c_int, c_double, c_ll,
-                                     ctypes.POINTER(c_int), ctypes.POINTER(c_ll)]),
+        "polfed_kpm_order": (c_int, [P_double, c_int, c_ll, c_double, c_int, c_double, c_int,
+                                     c_ll, ctypes.POINTER(c_int), ctypes.POINTER(c_ll)]),
+        "polfed_filter_coeffs": (c_int, [c_double, c_ll, c_int, P_double, P_double]),
+        "polfed_filter_order_damped": (c_int, [ctypes.POINTER(Model), c_double, c_double, c_double,
+                                               c_int, c_double, c_int, c_ll,
+                                               ctypes.POINTER(c_int), ctypes.POINTER(c_ll)]),
+        "polfed_set_filter_damping": (c_int, [c_void_p, c_int]),
         "polfed_dos_moments": (c_int, [c_void_p, ctypes.POINTER(Model), c_double, c_double,
                                        c_int, c_int, c_void_p, c_ull, P_double]),
         "polfed_s_rmt": (c_double, [c_int]),
@@ -212,15 +218,36 @@ def kpm_count(mu, N, x_lo, x_hi):
     return out.value
 
 
-def kpm_order(mu, N, sigma, nwin, p=0.17, max_order=0):
+def kpm_order(mu, N, sigma, nwin, p=0.17, max_order=0, damping=0):
     """(window count, K) of the order rule with the KPM density (polfed_kpm_order)."""
     mu = np.ascontiguousarray(mu, dtype=np.float64)
     nw = c_int()
     K = c_ll()
-    rc = LIB.polfed_kpm_order(mu.ctypes.data_as(P_double), len(mu), N, sigma, nwin, p, max_order,
-                              ctypes.byref(nw), ctypes.byref(K))
+    rc = LIB.polfed_kpm_order(mu.ctypes.data_as(P_double), len(mu), N, sigma, nwin, p, damping,
+                              max_order, ctypes.byref(nw), ctypes.byref(K))
     if rc != OK:
         raise PolfedError(rc, "polfed_kpm_order")
+    return nw.value, K.value
+
+
+def filter_coeffs(sigma, K, damping=0):
+    """(c[0..K], D) of the filter with the given damping (polfed_filter_coeffs)."""
+    c = np.empty(K + 1)
+    D = c_double()
+    rc = LIB.polfed_filter_coeffs(sigma, K, damping, c.ctypes.data_as(P_double), ctypes.byref(D))
+    if rc != OK:
+        raise PolfedError(rc, "polfed_filter_coeffs")
+    return c, D.value
+
+
+def filter_order_damped(model, E0w, E1w, sigma, nwin, damping, p=0.17, max_order=0):
+    """(window count, K) of the order rule for a damped filter."""
+    nw = c_int()
+    K = c_ll()
+    rc = LIB.polfed_filter_order_damped(ctypes.byref(model), E0w, E1w, sigma, nwin, p, damping,
+                                        max_order, ctypes.byref(nw), ctypes.byref(K))
+    if rc != OK:
+        raise PolfedError(rc, "polfed_filter_order_damped")
     return nw.value, K.value
 
 
@@ -432,6 +459,10 @@ class Context:
                                            None if R is None else _ptr(R), seed,
                                            mu.ctypes.data_as(P_double)), "dos_moments")
         return mu
+
+    def set_filter_damping(self, damping):
+        """DAMP_NONE or DAMP_JACKSON for apply_filter."""
+        self._check(LIB.polfed_set_filter_damping(self.h, damping), "set_filter_damping")
 
     def stream_copy(self, src, dst, reps=10):
         """Copy rate (GB/s, read + write) of the library's plain copy kernel

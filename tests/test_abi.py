@@ -174,3 +174,41 @@ def test_kpm_order_matches_oracle(L, W, J2, Delta, eps):
     assert nw2 > 30 and K2 <= cap
     assert K2 == kpm.choose_K(nw2, sig_t, 0.17, mu, N)
     assert kpm.choose_K(nw2 - 1, sig_t, 0.17, mu, N) > cap
+
+
+@pytest.mark.parametrize("sigma,K", [(0.0, 0), (0.0, 31), (0.37, 200), (-0.8, 5001)])
+def test_filter_coeffs_damped_match_oracle(sigma, K):
+    """polfed_filter_coeffs with and without Jackson damping against the
+    oracle's coefficients and normalisation."""
+    for damping in (0, 1):
+        c, D = pf.filter_coeffs(sigma, K, damping)
+        ref = chebyshev.filter_coeffs(sigma, K, damping)
+        assert np.abs(c - ref).max() <= 2e-15 * (K + 4)
+        Dref = chebyshev.norm_D(sigma, K, damping)
+        assert abs(D - Dref) <= 1e-12 * abs(Dref)
+    with pytest.raises(pf.PolfedError):
+        pf.filter_coeffs(0.1, 10, 2)
+
+
+@pytest.mark.parametrize("L,W,nwin,sigma", [(12, 3.0, 20, 0.0), (14, 1.0, 30, 0.3),
+                                            (16, 5.0, 10, -0.6)])
+def test_damped_order_matches_oracle(L, W, nwin, sigma):
+    """The order rule for the Jackson-damped filter (the library's closed
+    form of the damped lobe) against the oracle's (its definition sum),
+    integer-exact; and under a cap, the smallest window whose order fits."""
+    c = workloads.chain(L, W, 11)
+    m = pf.make_model(L, c.J1, c.J2, c.Delta, c.h)
+    E0w, E1w = -0.9 * L, 0.85 * L
+    N = comb(L, L // 2)
+    Ebar = -(c.J1 + c.J2) * c.Delta * L / (4.0 * (L - 1))
+    G = chebyshev.dos_gamma(L, c.J1, c.J2, c.Delta, c.h)
+    nw, K = pf.filter_order_damped(m, E0w, E1w, sigma, nwin, 1)
+    assert nw == nwin
+    assert K == chebyshev.choose_K(nwin, sigma, 0.17, N, Ebar, G, E0w, E1w, damping=1)
+    # undamped through the same call equals polfed_filter_order
+    assert pf.filter_order_damped(m, E0w, E1w, sigma, nwin, 0)[1] == \
+        pf.filter_order(m, E0w, E1w, sigma, nwin)[0]
+    cap = max(2, K // 3)
+    nw2, K2 = pf.filter_order_damped(m, E0w, E1w, sigma, nwin, 1, max_order=cap)
+    assert (nw2, K2) == chebyshev.capped_window(nwin, sigma, 0.17, N, Ebar, G, E0w, E1w, cap,
+                                                damping=1)

@@ -651,3 +651,58 @@ def test_kpm_choose_K_against_a_scan():
     K = kpm.choose_K(30, sig_t, 0.17, mu, H.shape[0])
     inside = int((chebyshev.P_of_x(a * w + b, sig_t, K) >= 0.17).sum())
     assert 27 <= inside <= 33
+
+
+# ---------------------------------------------------------------------------
+# optional Jackson-damped filter
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("K,sigma", [(7, 0.0), (40, 0.3), (201, -0.77), (500, 0.9)])
+def test_damped_filter_positive_and_a_single_level_density(K, sigma):
+    """The Jackson-damped filter is non-negative on [-1, 1], is 1 at sigma,
+    and is the KPM density of one level at sigma (moments T_n(sigma),
+    K + 1 of them) times pi sqrt(1 - x^2), up to its normalisation D."""
+    x = np.linspace(-0.9999, 0.9999, 3001)
+    P = chebyshev.P_of_x(x, sigma, K, damping=1)
+    assert P.min() > -1e-13
+    assert abs(chebyshev.P_of_x(sigma, sigma, K, damping=1)[0] - 1.0) < 1e-12
+    mu = np.cos(np.arange(K + 1) * np.arccos(sigma))
+    rho = kpm.density(mu, x)
+    D = chebyshev.norm_D(sigma, K, damping=1)
+    assert np.abs(P * D - pi * np.sqrt(1.0 - x * x) * rho).max() < 1e-10 * D
+
+
+@pytest.mark.parametrize("K", [400, 4000])
+def test_damped_lobe_edges_hit_p_and_width(K):
+    """The damped lobe edges sit at P = p, and their half-width in theta
+    tends to 1.8265 pi/(K+2) (the closed form of the damped kernel,
+    (E(u+b) + E(u-b))^2 with E(u) = sin(M u/2)/sin(u/2), b = pi/(M+1),
+    M = K+1, against the definition sum used for the edges)."""
+    for sigma in (0.0, 0.5):
+        x_lo, x_hi = chebyshev.lobe_edges(sigma, K, 0.17, damping=1)
+        for xe in (x_lo, x_hi):
+            assert abs(chebyshev.P_of_x(xe, sigma, K, damping=1)[0] - 0.17) < 1e-9
+        a = np.arccos(sigma)
+        M, b = K + 1, pi / (K + 2)
+
+        def E(u):
+            return np.sin(M * u / 2) / np.sin(u / 2)
+
+        def F(u):
+            return (E(u + b) + E(u - b)) ** 2
+        t = np.arccos(x_lo) - a
+        closed = (F(t) + F(2 * a + t)) / (F(1e-9) + F(2 * a + 1e-9))
+        assert abs(closed - 0.17) < 1e-6
+        assert abs(t * (K + 2) / pi - 1.8265) < 0.01
+
+
+def test_damped_choose_K_against_a_scan():
+    """With damping the order rule is still max{K : n_P(K) >= nwin}: against
+    a linear scan (Gaussian DOS, N = 200, sigma~ = 0.1)."""
+    args = (0.1, 0.17, 200, 0.0, 2.0, -8.0, 8.0)
+    K = chebyshev.choose_K(20, *args, damping=1)
+    assert 20 < K < 400
+    f = [chebyshev.n_P(k, *args, damping=1) for k in range(1, 500)]
+    assert K == max(k for k, v in zip(range(1, 500), f) if v >= 20)
+    # the damped lobe is wider, so the same window takes a higher order
+    assert K > chebyshev.choose_K(20, *args)
