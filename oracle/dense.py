@@ -14,7 +14,8 @@ diagonalisation:
   eigenvalues in an interval around the target; this is still the full
   dense reduction of H, only the tridiagonal eigenvalues outside the window
   are not computed.  This is the practical definition at L = 18
-  (N = 48,620: 19 GB of FP64 and about 50 CPU-minutes on 8 cores).
+  (N = 48,620: 19 GB of FP64 and about 50 CPU-minutes on 8 cores).  Both
+  are pinned against the free-fermion spectrum of the XX chain at L = 12.
 
 Ties in distance go to the lower eigenvalue; output is ascending.
 """

@@ -385,6 +385,31 @@ def test_shift_invert_matches_dense():
     assert np.abs(H @ V - V * b).max() < 1e-9
 
 
+def test_window_eigenvalues_against_free_fermions():
+    """eigenvalues_in_window and nearest_dense_window (the definition at the
+    sizes where only a window of the dense spectrum is taken) on the L = 12
+    XX chain, whose whole spectrum is the free-fermion sums: the window holds
+    exactly the sums in (lo, hi], and the nearest set, its size and the gap to
+    the first value left out follow from a plain sort of those sums."""
+    L = 12
+    H = chain.hamiltonian_csr(L, 1.0, 0.0, 0.0, np.zeros(L))
+    ff = _free_fermion_spectrum(L)
+    # centres between levels (and one on a degenerate level, where ties go
+    # to the lower value and every copy of it is kept or dropped together)
+    for sig, hw, nev in [(0.37, 0.9, 25), (-1.21, 0.6, 7), (0.0, 0.5, 40)]:
+        lo, hi = sig - hw, sig + hw
+        want = ff[(ff > lo + 1e-9) & (ff <= hi - 1e-9)]
+        got = dense.eigenvalues_in_window(H, lo, hi)
+        assert len(got) == len(want) and np.abs(got - want).max() < 1e-12
+        keep, nd, cnt = dense.nearest_dense_window(H, sig, nev, hw)
+        assert cnt == len(want)
+        d = sorted(want, key=lambda e: (abs(e - sig), e))
+        assert np.abs(keep - np.sort(d[:nev])).max() < 1e-12
+        assert abs(nd - abs(d[nev] - sig)) < 1e-12
+    with pytest.raises(ValueError):
+        dense.nearest_dense_window(H, 0.37, 10, 0.01)
+
+
 def test_seed_and_block_invariance():
     L, nev = 12, 10
     h = workloads.fields(L, 2.5, 21)
