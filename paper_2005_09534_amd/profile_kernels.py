@@ -27,6 +27,8 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 COPY_BYTES = 1 << 30
+# order of the untimed filter that loads the kernels' code before the timed one
+WARMUP_K = 2
 
 
 STEP_SOURCES = ("hv_kernels.h", "hv.hip", "hv_f32.hip")
@@ -74,7 +76,7 @@ def run(args):
                            *[int(v) for v in args.shape.split(",")])
     ctx.set_graphs(False)  # one dispatch per step, each counted
     # a short filter first, so that loading the kernels' code is not timed
-    ctx.apply_filter(m, E0w, E1w, sigma, 2, X, out=Y)
+    ctx.apply_filter(m, E0w, E1w, sigma, WARMUP_K, X, out=Y)
     torch.cuda.synchronize()
     ctx.filter_stats(reset=True)
     ctx.apply_filter(m, E0w, E1w, sigma, args.K, X, out=Y)
@@ -95,8 +97,9 @@ def run(args):
 
 def _read(path, counter, step_name):
     """(per-dispatch values of `counter` for the step kernel instantiation
-    `step_name`, largest value for the runtime's device-to-device copy
-    kernel) from a rocprofv3 counter_collection CSV."""
+    `step_name` in the timed filter, largest value for the library's copy
+    kernel) from a rocprofv3 counter_collection CSV.  The WARMUP_K + 1
+    dispatches of the warm-up filter come first and are left out."""
     step, copy = [], []
     with open(path) as f:
         for row in csv.DictReader(f):
@@ -105,9 +108,10 @@ def _read(path, counter, step_name):
                 continue
             v = float(row.get("Counter_Value") or 0.0)
             if step_name in name:
-                step.append(v)
+                step.append((int(row.get("Dispatch_Id") or len(step)), v))
             elif "k_stream_copy" in name:
                 copy.append(v)
+    step = [v for _, v in sorted(step)[WARMUP_K + 1:]]
     return step, (max(copy) if copy else 0.0)
 
 
