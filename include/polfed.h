@@ -441,11 +441,18 @@ int polfed_solve(polfed_ctx *ctx, const polfed_model *model,
  * many independent runs) solved together: models[R] may mix L.  evals and
  * resid are [R x nev] (realisation-major); evecs NULL or the concatenation
  * of the per-realisation [dim_r x nev] column-major blocks; infos (nullable)
- * [R]; status[R] per realisation.  Returns the worst status.  R >= 1 and
+ * [R]; status[R] per realisation: POLFED_OK, POLFED_NOT_CONVERGED, or the
+ * member's own error (POLFED_EBOUNDS after the retries below,
+ * POLFED_EBREAKDOWN, POLFED_EINVAL), which ends that member only, its
+ * outputs left untouched.  Returns POLFED_OK when every member is OK, else
+ * POLFED_NOT_CONVERGED; an error of the device or its memory ends the call
+ * and is returned.  R >= 1 and
  * 1 <= nev <= dim_r for every model, checked before any work (else
  * POLFED_EINVAL with the outputs untouched).  Window doubling and FP64
  * re-solves as in polfed_solve, each run for the members concerned as a
- * batch of its own.  Realisations with one block size and the same J2 != 0
+ * batch of its own; a member whose filter left [-1, 1] is solved again with
+ * the bounds margin eta doubled (three times at most), as in polfed_solve.
+ * Realisations with one block size and the same J2 != 0
  * share every filter launch whatever their L (one batched step kernel walks
  * all their row tiles), and the FP64 refinement filters of the FP32 mode
  * run batched in the same way.  With opts->block_size = 0 each chain

@@ -44,6 +44,7 @@
 // Included by hv.hip (FP64 instantiations, casts) and hv_f32.hip (FP32
 // instantiations), which compile in parallel.
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "internal.h"
@@ -386,20 +387,36 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
   const int wave = threadIdx.x >> 6;
   const int slot = lane / G;
   const int col = (lane % G) * VEC;
-  for (long long t = t_begin; t < t_end; t += t_step) {
-    // the realisation holding tile t: the last item with tile0 <= t
+  // the realisation holding tile t is the last item with tile0 <= t: a
+  // binary search for this group's first tile, then, as t only grows, a
+  // forward scan (the tile range of one realisation spans many steps of t)
+  int i = 0;
+  {
     int lo = 0, hi = B - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (items[mid].tile0 <= t)
+      if (items[mid].tile0 <= t_begin)
         lo = mid;
       else
         hi = mid - 1;
     }
-    const int i = lo;
+    i = lo;
+  }
+  long long next0 = (i + 1 < B) ? items[i + 1].tile0 : LLONG_MAX;
+  for (long long t = t_begin; t < t_end; t += t_step) {
+    while (t >= next0) {
+      ++i;
+      next0 = (i + 1 < B) ? items[i + 1].tile0 : LLONG_MAX;
+    }
     const BatchItem<T> it = items[i];
     const long long ji = j - (Kmax - it.K);
-    if (!it.active || ji < 0) continue;
+    if (!it.active || ji < 0) {
+      // the realisation idles at this step: jump past the rest of its tiles
+      // (a batch spends many steps with most of its members idle)
+      if (next0 >= t_end) break;
+      t += ((next0 - t + t_step - 1) / t_step - 1) * t_step;
+      continue;
+    }
     const long long r = (t - it.tile0) * rows_per_iter + (long long)wave * RPW + slot;
     if (r >= it.n) continue;
     StepArgs<T> a = base;
@@ -444,7 +461,7 @@ __global__ __launch_bounds__(MAXT) void k_step_batched(StepArgs<T> base, const B
       a.gamma = (T)(-it.Dinv);
     }
     if (LDS_TAB) {
-      const int32_t *tA = s_tab + bt.off[it.tab];
+      const int32_t *tA = s_tab + it.taboff;
       step_row<T, S, LPL, EARLY, 0>(a, r, col, tA,
                                     reinterpret_cast<const uint16_t *>(tA + (1 << it.half)), tC);
     } else {

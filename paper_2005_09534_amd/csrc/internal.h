@@ -198,7 +198,7 @@ struct BatchItem {
   // first row tile of this realisation in the launch's tile range (tiles of
   // batched_tile_rows rows, realisations in item order)
   long long tile0;
-  int tab;  // its entry in the launch's BatchTables (when staged in LDS)
+  int taboff;  // int32 offset of its tables in the launch's LDS staging (BatchTables.off)
 };
 
 // The distinct rank tables of a batched launch (one per chain length), all

@@ -1510,7 +1510,7 @@ static BatchTables batch_tables(std::vector<BatchItem<T>> &items,
       bt.ints += (1 << b->half) + (1 << b->half) / 2;
       f = idx.emplace(b, k).first;
     }
-    items[i].tab = f->second;
+    items[i].taboff = bt.off[f->second];
   }
   if ((size_t)bt.ints * sizeof(int32_t) > (size_t)96 * 1024) std::memset(&bt, 0, sizeof(bt));
   return bt;
