@@ -99,11 +99,6 @@ def hamiltonian_csr(L, J1, J2, Delta, h):
     return H
 
 
-def apply_h(H, X):
-    """Y = H X for an (n x s) block (plain sparse product)."""
-    return H @ X
-
-
 def hamiltonian_row(L, J1, J2, Delta, h, s):
     """Row of H for one basis state s, by the literal sum of eq. (XXZ):
     returns {state': value} (the diagonal under s itself).  For sampled
