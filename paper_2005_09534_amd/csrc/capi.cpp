@@ -300,6 +300,8 @@ int polfed_dos_moments(polfed_ctx *ctx, const polfed_model *m, double E0w, doubl
   return guarded(ctx, [&] {
     PF_REQUIRE(mu != nullptr, "mu is NULL");
     PF_REQUIRE(E1w > E0w, "E1w must exceed E0w");
+    PF_REQUIRE(nmom >= 1 && nmom <= (1 << 20), "dos moments: nmom must be in [1, 2^20]");
+    PF_REQUIRE(nvec >= 1, "dos moments: nvec must be >= 1");
     Chain c;
     make_chain(ctx, m, c);
     const double a = 2.0 / (E1w - E0w), b = -(E0w + E1w) / (E1w - E0w);
